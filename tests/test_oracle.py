@@ -1,0 +1,281 @@
+"""Pins of the CPU oracle against values and facts fixed independently of it:
+brute force over a different construction, the paper's printed numbers
+(tests/golden/), closed forms and invariants.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import golden_io
+
+E = oracle.EMPTY
+
+
+# --------------------------------------------------------------------------
+# counts
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_count_matches_row_permutation_brute_force(n):
+    assert oracle.count(n, oracle.identity_prefix(n)) == oracle.brute_force_count(n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_unnormalised_matches_brute_force(n):
+    empty = np.full(n * n, E, dtype=np.uint8)
+    assert oracle.count(n, empty) == oracle.brute_force_count(n, normalized=False)
+
+
+def test_task_stated_totals():
+    g = golden_io.counts()
+    for n in (4, 5):
+        fixed = oracle.count(n, oracle.identity_prefix(n))
+        assert oracle.total_from_fixed(n, fixed) == g[(n, "total")]
+        assert oracle.count(n, np.full(n * n, E, np.uint8)) == g[(n, "total")]
+
+
+def test_closed_forms():
+    # N=1: the single cell; N=2,3: no diagonal Latin square exists
+    assert oracle.count(1, [0]) == 1
+    assert oracle.count(2, oracle.identity_prefix(2)) == 0
+    assert oracle.count(3, oracle.identity_prefix(3)) == 0
+
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_first_row_normalisation(n):
+    # every first row occurs equally often: total = N! * fixed-first-row count
+    fixed = oracle.count(n, oracle.identity_prefix(n))
+    total = oracle.count(n, np.full(n * n, E, np.uint8))
+    assert total == math.factorial(n) * fixed
+
+
+def test_relabel_invariance_order7():
+    rng = np.random.default_rng(170902599)
+    base = oracle.count(7, oracle.identity_prefix(7))
+    for _ in range(2):
+        p = oracle.identity_prefix(7)
+        p[:7] = rng.permutation(7)
+        assert oracle.count(7, p) == base
+
+
+def test_full_squares_are_dls():
+    # a complete square counts 1 exactly when it satisfies the definition
+    n = 5
+    rows = oracle.assignments(n, oracle.identity_prefix(n), list(range(n, n * n)))
+    assert rows.shape[0] == 8
+    for sq in rows:
+        assert oracle.is_dls(n, sq)
+        assert oracle.count(n, sq) == 1
+    bad = rows[0].copy()
+    bad[[n + 0, n + 1]] = bad[[n + 1, n + 0]]        # break two columns
+    assert oracle.count(n, bad) == 0
+    assert not oracle.is_dls(n, bad)
+
+
+def test_inconsistent_prefix_counts_zero():
+    p = oracle.identity_prefix(6)
+    p[6 + 1] = 0           # (1,1) = 0 clashes with (0,0) on the main diagonal
+    assert oracle.count(6, p) == 0
+    p = oracle.identity_prefix(6)
+    p[6 + 4] = 4           # (1,4) = 4 clashes with (0,4) in column 4
+    assert oracle.count(6, p) == 0
+
+
+def test_invalid_input_rejected():
+    with pytest.raises(ValueError):
+        oracle.count(4, [0, 1, 2, 7] + [E] * 12)
+
+
+def test_split_additivity_order7():
+    # sum over the children of a workunit split equals the parent's count
+    n = 7
+    parent = oracle.identity_prefix(n)
+    cells = [8, 16, 24, 32, 40, 48]                   # the main diagonal
+    kids = oracle.assignments(n, parent, cells)
+    assert kids.shape[0] > 0
+    assert int(oracle.count_many(n, kids).sum()) == oracle.count(n, parent)
+
+
+def _set_based_assignments(n, cells):
+    """Independent count of consistent assignments using Python sets."""
+    sq = {(0, j): j for j in range(n)}
+
+    def ok(i, j, v):
+        for (a, b), w in sq.items():
+            if w == v and (a == i or b == j or (i == j and a == b)
+                           or (i + j == n - 1 and a + b == n - 1)):
+                return False
+        return True
+
+    def rec(k):
+        if k == len(cells):
+            return 1
+        i, j = cells[k]
+        total = 0
+        for v in range(n):
+            if ok(i, j, v):
+                sq[(i, j)] = v
+                total += rec(k + 1)
+                del sq[(i, j)]
+        return total
+    return rec(0)
+
+
+def test_decomposition_counts_match_set_based_enumeration():
+    for n, k in ((7, 8), (8, 7)):
+        order = oracle.fill_order(n)
+        assert oracle.count_assignments(n, oracle.identity_prefix(n), order[:k]) == \
+            _set_based_assignments(n, [divmod(c, n) for c in order[:k]])
+
+
+def test_order9_decomposition_size():
+    # Sec. 5.2 decomposes order 9 on the first 10 cells of the Fig. 1 order.
+    # The paper prints 1 225 884 workunits; every consistent assignment of
+    # those cells (the oracle, and separately a set-based enumeration run
+    # once offline) gives 1 255 884 -- exactly 30 000 more, which reads as a
+    # misprint of one digit.  No extra pruning (empty candidate domains) closes
+    # the gap.  The reproducible value is pinned here.
+    order = golden_io.fig1_order()
+    assert oracle.count_assignments(9, oracle.identity_prefix(9), order[:10]) == 1255884
+
+
+# --------------------------------------------------------------------------
+# vertical symmetry
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_vs_matches_brute_force(n):
+    assert oracle.count(n, oracle.identity_prefix(n), vs=True) == \
+        oracle.brute_force_count(n, vs=True)
+
+
+@pytest.mark.parametrize("n", [4])
+def test_vs_unnormalised(n):
+    fixed = oracle.count(n, oracle.identity_prefix(n), vs=True)
+    assert oracle.brute_force_count(n, normalized=False, vs=True) == \
+        oracle.total_from_fixed(n, fixed, vs=True)
+
+
+def test_vs_odd_orders_are_empty():
+    for n in (3, 5, 7):
+        assert oracle.count(n, oracle.identity_prefix(n), vs=True) == 0
+
+
+def test_vs_order4_both_normalised_dls_are_vs():
+    assert oracle.count(4, oracle.identity_prefix(4), vs=True) == \
+        oracle.count(4, oracle.identity_prefix(4)) == 2
+
+
+# --------------------------------------------------------------------------
+# fill order (Sec. 2.3)
+# --------------------------------------------------------------------------
+
+def test_fill_order_reproduces_fig1():
+    assert oracle.fill_order(9) == golden_io.fig1_order()
+
+
+def test_fill_order_without_forced_rule_would_differ():
+    # sanity of the fixture: the forced rule matters at position 13
+    order = golden_io.fig1_order()
+    assert divmod(order[12], 9) == (8, 0)
+
+
+# --------------------------------------------------------------------------
+# M-transformations and hourglass classes (Sec. 4)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9, 10])
+def test_group_order(n):
+    m = n // 2
+    p, q = oracle.hourglass_group(n)
+    assert len(p) == 2 * 2 ** m * math.factorial(m - 1)
+    rho = np.arange(n)[::-1]
+    for pi, qi in zip(p, q):
+        assert sorted(pi) == list(range(n))
+        assert set(pi[[0, n - 1]]) == {0, n - 1}
+        assert np.array_equal(pi[rho], rho[pi])          # p commutes with the mirror
+        assert np.array_equal(qi, pi) or np.array_equal(qi, rho[pi])
+
+
+def test_full_class_bound():
+    # Sec. 4.1: adding the row-0/other-row swaps and the diagonal mirror gives
+    # 4 * 2^m * m! (1536 for N=9, 15360 for N=10); the hourglass group is the
+    # subgroup fixing {row 0, row N-1} and excluding diagonal mirrors
+    for n, full in ((9, 1536), (10, 15360)):
+        m = n // 2
+        assert 4 * 2 ** m * math.factorial(m) == full
+        assert len(oracle.hourglass_group(n)[0]) * 2 * m == full
+
+
+def _renormalise(n, t):
+    t = np.asarray(t, dtype=np.int64)
+    rename = {int(t[j]): j for j in range(n)}
+    return np.array([E if v == E else rename[int(v)] for v in t], dtype=np.uint8)
+
+
+def test_fig2_vertical_mirror():
+    left, right = golden_io.fig2()
+    n = 10
+    assert oracle.count_assignments(n, left, []) == 1          # consistent design
+    p, q = oracle.hourglass_group(n)
+    rho = np.arange(n)[::-1]
+    g = [k for k in range(len(p)) if np.array_equal(p[k], np.arange(n))
+         and np.array_equal(q[k], rho)]
+    assert len(g) == 1
+    assert np.array_equal(oracle.apply(n, g[0], left), _renormalise(n, right))
+
+
+def test_hourglass_pins_order8():
+    pins = golden_io.keyed("hourglass_n8.txt")
+    nh, reps, mult = oracle.hourglass_classes(8)
+    assert nh == pins["hourglasses"]
+    assert len(reps) == pins["classes"]
+    assert int(mult.max()) == pins["max_class"]
+    assert int(mult.astype(np.int64).sum()) == nh
+
+
+@pytest.mark.parametrize("n", [5, 6, 7])
+def test_proposition1(n):
+    # completions of H and of mu(H) are equinumerous (Sec. 4.2, Prop. 1)
+    rng = np.random.default_rng(1709 + n)
+    _, reps, _ = oracle.hourglass_classes(n)
+    p, _ = oracle.hourglass_group(n)
+    for h in reps[rng.choice(len(reps), size=min(6, len(reps)), replace=False)]:
+        c = oracle.count(n, h)
+        for g in rng.choice(len(p), size=4, replace=False):
+            assert oracle.count(n, oracle.apply(n, int(g), h)) == c
+
+
+@pytest.mark.parametrize("n", [5, 6, 7])
+def test_symmetry_broken_total_equals_plain(n):
+    _, reps, mult = oracle.hourglass_classes(n)
+    c = oracle.count_many(n, reps)
+    assert int((c.astype(object) * mult.astype(object)).sum()) == \
+        oracle.count(n, oracle.identity_prefix(n))
+
+
+def test_canonical_reps_are_orbit_minima():
+    n = 7
+    _, reps, mult = oracle.hourglass_classes(n)
+    p, _ = oracle.hourglass_group(n)
+    for h, m in zip(reps[:20], mult[:20]):
+        imgs = {bytes(oracle.apply(n, g, h)) for g in range(len(p))}
+        assert len(imgs) == m
+        assert min(imgs) == bytes(h)
+
+
+@pytest.mark.slow
+def test_symmetry_broken_total_order8_matches_paper():
+    _, reps, mult = oracle.hourglass_classes(8)
+    c = oracle.count_many(8, reps)
+    total = int((c.astype(object) * mult.astype(object)).sum())
+    assert total == golden_io.counts()[(8, "fixed")]
+
+
+@pytest.mark.parametrize("n", [6])
+def test_vs_symmetry_broken_total(n):
+    _, reps, mult = oracle.hourglass_classes(n, vs=True)
+    c = oracle.count_many(n, reps, vs=True)
+    assert int((c.astype(object) * mult.astype(object)).sum()) == \
+        oracle.count(n, oracle.identity_prefix(n), vs=True)
