@@ -1,0 +1,177 @@
+/*
+ * dls.h -- C ABI of the MI355X (gfx950) library that counts diagonal Latin
+ * squares (DLS) exactly.
+ *
+ * Method: Kochemazov, Vatutin, Zaikin, "Fast Algorithm for Enumerating
+ * Diagonal Latin Squares of Small Order" (arXiv:1709.02599).
+ *
+ * Conventions shared by every entry point
+ *  - A square of order n (1 <= n <= 16) is n*n uint8 cells, row-major; a cell
+ *    holds a value 0..n-1 or DLS_EMPTY.  A "prefix" is such a square with some
+ *    cells assigned; its count is the exact number of DLS that agree with it
+ *    (definition: Sec. 1).  A prefix that breaks a constraint is not an error:
+ *    its count is 0.
+ *  - All buffers are owned by the caller.  The library keeps no pointer to a
+ *    caller buffer after the call returns (the *_async calls: after the work
+ *    enqueued on the stream completes).
+ *  - Every entry point returns DLS_OK (0) or a negative DLS_E* code; nothing
+ *    is thrown across the ABI.  dls_strerror() names a code.
+ *  - Host planning calls (dls_order, dls_split*, dls_group_order) need no GPU.
+ *    Counting calls run on the current HIP device.
+ */
+#ifndef DLS_H
+#define DLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DLS_EMPTY 0xFFu
+#define DLS_MAXN 16
+
+/* flags */
+enum {
+    /* vertical symmetry a[i][j] + a[i][n-1-j] = n-1 (Sec. 1; Sec. 5.4).
+     * Only the left half is searched; each value also fixes its mirror. */
+    DLS_VSYM = 1u << 0,
+    /* dls_split only: symmetry breaking on hourglass designs (Sec. 4.2-4.3,
+     * Alg. 5-6).  Emits only prefixes whose hourglass is canonical, each with
+     * the power of its class in mult_out. */
+    DLS_SYMBREAK = 1u << 1,
+    /* counting: use the plain one-prefix-per-lane kernel instead of the
+     * persistent work-stealing kernel (both give identical counts). */
+    DLS_PLAIN = 1u << 2
+};
+
+/* error codes */
+enum {
+    DLS_OK = 0,
+    DLS_EINVAL = -1,   /* bad n, depth, flags, cell value or pointer          */
+    DLS_ERANGE = -2,   /* output capacity too small (required size reported)  */
+    DLS_ENOMEM = -3,   /* host or device allocation failed                    */
+    DLS_EDEVICE = -4,  /* HIP runtime error, no device, or kernel fault flag  */
+    DLS_EPATTERN = -5  /* a prefix's assigned cells differ from the pattern   */
+};
+
+const char *dls_strerror(int err);
+
+/* Library version string, e.g. "dls-mi355x 1.0 (gfx950)". */
+const char *dls_version(void);
+
+/*
+ * Fill order of the empty cells (Sec. 2.3, Fig. 1).  Starting from the
+ * assigned cells (assigned[c] != 0 for c in 0..n*n-1), repeatedly: if a row,
+ * column, main diagonal or antidiagonal has exactly n-1 assigned cells, its
+ * last cell is next (row-major-first if several); otherwise the cell with the
+ * largest V = r_i + c_j + md + ad (Sec. 2.3), ties broken row-major.
+ * DLS_VSYM: only left-half cells (j < n/2, or j <= n/2 for odd n) are listed;
+ * each also assigns its mirror.  DLS_SYMBREAK: the hourglass cells (rows 0 and
+ * n-1, both diagonals; Sec. 4.2) come before all others.
+ * order_out: capacity n*n; receives flat cell indices i*n+j; *len_out gets the
+ * number written.
+ */
+int dls_order(int n, uint32_t flags, const uint8_t *assigned, uint8_t *order_out,
+              int *len_out);
+
+/*
+ * Split into independent workunits (Sec. 5.2).  Starts from row 0 = 0..n-1
+ * and assigns the next `depth` cells of the dls_order() sequence in every way
+ * that keeps all constraints among assigned cells, in depth-first order with
+ * values increasing.  Two-call pattern: with prefixes_out == NULL only
+ * *num_out = P (the number of prefixes) is set.  Otherwise prefixes_out is
+ * [cap][n*n] uint8 and mult_out [cap] uint32 or NULL; returns DLS_ERANGE with
+ * *num_out = P if cap < P.
+ * DLS_SYMBREAK: depth must cover the hourglass (>= 3n-3 plain, fewer left-half
+ * cells with DLS_VSYM); only prefixes whose hourglass is its class's
+ * lexicographically least member are emitted, with mult_out = class power,
+ * so that sum(mult * count) is the fixed-first-row total (Corollary 1).
+ * Without it mult_out is all 1.
+ */
+int dls_split(int n, uint32_t flags, int depth, uint8_t *prefixes_out, uint32_t *mult_out,
+              int64_t cap, int64_t *num_out);
+
+/* As dls_split, but starting from an arbitrary prefix `base` (n*n cells)
+ * instead of the bare first row; DLS_SYMBREAK is not accepted.  With
+ * DLS_VSYM, `base` is first completed by mirror pairs (an inconsistent pair
+ * yields P = 0). */
+int dls_split_from(int n, uint32_t flags, const uint8_t *base, int depth,
+                   uint8_t *prefixes_out, int64_t cap, int64_t *num_out);
+
+/* Uniform sampling of workunits (Sec. 5.3 estimates from a random sample):
+ * the prefixes that dls_split(n, flags, depth) would emit at the positions
+ * listed in `indices` (k strictly increasing 0-based positions) are written to
+ * prefixes_out [k][n*n]; *total_out gets P.  Streams the split without
+ * storing it.  DLS_SYMBREAK is not accepted.  Returns DLS_ERANGE if an index
+ * is >= P. */
+int dls_split_sample(int n, uint32_t flags, int depth, const int64_t *indices, int64_t k,
+                     uint8_t *prefixes_out, int64_t *total_out);
+
+/* Order of the hourglass transformation group used by DLS_SYMBREAK
+ * (2 * 2^(n/2) * (n/2 - 1)!, Sec. 4.3 Alg. 5), or a negative error. */
+int64_t dls_group_order(int n);
+
+/* Canonicity test of one hourglass design h (n*n cells; rows 0 and n-1 and
+ * both diagonals assigned, row 0 = 0..n-1): 0 if some transformed and
+ * renormalised image is lexicographically smaller (row-major), else the class
+ * power (Alg. 5).  Written to *mult_out. */
+int dls_canon(int n, const uint8_t *h, uint32_t *mult_out);
+
+/*
+ * Exact counts on the GPU, host buffers, blocking.  prefixes: [num][n*n];
+ * counts_out: [num] uint64, counts_out[k] = number of DLS (VS-DLS with
+ * DLS_VSYM) agreeing with prefixes[k].  Prefixes may differ in which cells
+ * are assigned; they are grouped by pattern internally.  DLS_PLAIN selects
+ * the plain kernel.  With DLS_VSYM and odd n > 1 every count is 0 and nothing
+ * is launched.
+ */
+int dls_count(int n, uint32_t flags, const uint8_t *prefixes, int64_t num,
+              uint64_t *counts_out);
+
+/* Launch shape for the *_ex calls; zero fields mean "library default". */
+typedef struct {
+    int block;          /* threads per workgroup (64..1024, multiple of 64)   */
+    int blocks_per_cu;  /* persistent kernel: resident workgroups per CU      */
+    int steal_depth;    /* persistent kernel: donate only levels < end-this   */
+    int refill_every;   /* persistent kernel: DFS steps between refills       */
+} dls_launch;
+
+/*
+ * Exact counts on the GPU, device buffers, asynchronous on `stream`
+ * (a hipStream_t; NULL = default stream).  All prefixes must assign exactly
+ * the cells marked in `pattern` (host array of n*n bytes, nonzero = assigned;
+ * NULL = "row 0 only"), so that one fill order serves the whole batch.
+ * d_prefixes: device [num][n*n] uint8; d_counts: device [num] uint64,
+ * overwritten.  d_status: optional device uint32, OR-ed with 1 if a prefix
+ * does not match the pattern (its count is then 0) and with 2 if the
+ * persistent kernel's bounded waits expired; may be NULL.
+ * Returns after enqueueing (host-side argument errors are returned at once).
+ */
+int dls_count_async(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes,
+                    int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream);
+
+int dls_count_async_ex(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes,
+                       int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream,
+                       const dls_launch *launch);
+
+/* As dls_count_async_ex; in addition, when d_steps != NULL, the number of
+ * DFS steps taken by all lanes is added into *d_steps (device uint64).  A
+ * step either enters a cell with a candidate value or returns from a cell
+ * whose candidates are exhausted; the count feeds the operation-count model
+ * behind the roofline figures. */
+int dls_count_async_stats(int n, uint32_t flags, const uint8_t *pattern,
+                          const uint8_t *d_prefixes, int64_t num, uint64_t *d_counts,
+                          uint32_t *d_status, void *stream, const dls_launch *launch,
+                          uint64_t *d_steps);
+
+/* Integer-VALU throughput probe: `iters` rounds of independent 32-bit
+ * and/or/xor/add chains on every lane of `blocks` x 256 threads; d_sink gets
+ * one word per thread.  Used to measure the achievable integer-op peak. */
+int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLS_H */

@@ -1,0 +1,243 @@
+"""Python binding of libdls.so (include/dls.h): exact counting of diagonal
+Latin squares on MI355X (gfx950).
+
+The functions below carry the C ABI's names and only marshal arguments:
+NumPy arrays for host buffers, torch tensors (``.data_ptr()``) for device
+buffers and ``torch.cuda.Stream`` (or a raw handle) for streams.  Every step
+of the count runs in the HIP library; there is no Python or CPU fallback.
+If the library has not been built, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "DLS_VSYM", "DLS_SYMBREAK", "DLS_PLAIN", "DLS_EMPTY", "DLSError", "LIB_PATH",
+    "dls_version", "dls_strerror", "dls_order", "dls_split", "dls_split_from",
+    "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async",
+    "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
+]
+
+DLS_VSYM = 1 << 0
+DLS_SYMBREAK = 1 << 1
+DLS_PLAIN = 1 << 2
+DLS_EMPTY = 0xFF
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdls.so")
+
+
+class DLSError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {dls_strerror(code)} ({code})")
+        self.code = code
+
+
+class DlsLaunch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
+                ("steal_depth", ctypes.c_int), ("refill_every", ctypes.c_int)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc, gfx950) before using paper_1709_02599_amd")
+    lib = ctypes.CDLL(LIB_PATH)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vp = ctypes.c_void_p
+    sig = {
+        "dls_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "dls_version": (ctypes.c_char_p, []),
+        "dls_order": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, u8p,
+                                     ctypes.POINTER(ctypes.c_int)]),
+        "dls_split": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, u8p, u32p,
+                                     ctypes.c_int64, i64p]),
+        "dls_split_from": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int, u8p,
+                                          ctypes.c_int64, i64p]),
+        "dls_split_sample": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, i64p,
+                                            ctypes.c_int64, u8p, i64p]),
+        "dls_group_order": (ctypes.c_int64, [ctypes.c_int]),
+        "dls_canon": (ctypes.c_int, [ctypes.c_int, u8p, u32p]),
+        "dls_count": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_uint64)]),
+        "dls_count_async": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp, ctypes.c_int64,
+                                           vp, vp, vp]),
+        "dls_count_async_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp,
+                                              ctypes.c_int64, vp, vp, vp,
+                                              ctypes.POINTER(DlsLaunch)]),
+        "dls_count_async_stats": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp,
+                                                 ctypes.c_int64, vp, vp, vp,
+                                                 ctypes.POINTER(DlsLaunch), vp]),
+        "dls_valu_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _u8(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise DLSError(rc, what)
+
+
+def _square(n: int, cells) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(cells, dtype=np.uint8).reshape(n * n))
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (or an int), None for None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def dls_strerror(code: int) -> str:
+    return _lib.dls_strerror(code).decode()
+
+
+def dls_version() -> str:
+    return _lib.dls_version().decode()
+
+
+def dls_order(n: int, flags: int = 0, assigned=None) -> list:
+    """Fill order of the empty cells (flat indices).  ``assigned`` defaults to
+    row 0."""
+    if assigned is None:
+        assigned = np.zeros(n * n, dtype=np.uint8)
+        assigned[:n] = 1
+    a = _square(n, assigned)
+    out = np.zeros(max(1, n * n), dtype=np.uint8)
+    ln = ctypes.c_int(0)
+    _check(_lib.dls_order(n, flags, _u8(a), _u8(out), ctypes.byref(ln)), "dls_order")
+    return [int(x) for x in out[:ln.value]]
+
+
+def dls_split(n: int, flags: int, depth: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Workunit prefixes [P, n*n] uint8 and class powers [P] uint32."""
+    num = ctypes.c_int64(0)
+    _check(_lib.dls_split(n, flags, depth, None, None, 0, ctypes.byref(num)), "dls_split")
+    p = num.value
+    pre = np.zeros((p, n * n), dtype=np.uint8)
+    mult = np.zeros(p, dtype=np.uint32)
+    if p:
+        _check(_lib.dls_split(n, flags, depth, _u8(pre),
+                              mult.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), p,
+                              ctypes.byref(num)), "dls_split")
+    return pre, mult
+
+
+def dls_split_from(n: int, flags: int, base, depth: int) -> np.ndarray:
+    b = _square(n, base)
+    num = ctypes.c_int64(0)
+    _check(_lib.dls_split_from(n, flags, _u8(b), depth, None, 0, ctypes.byref(num)),
+           "dls_split_from")
+    p = num.value
+    pre = np.zeros((p, n * n), dtype=np.uint8)
+    if p:
+        _check(_lib.dls_split_from(n, flags, _u8(b), depth, _u8(pre), p, ctypes.byref(num)),
+               "dls_split_from")
+    return pre
+
+
+def dls_split_sample(n: int, flags: int, depth: int,
+                     indices: Sequence[int]) -> Tuple[np.ndarray, int]:
+    idx = np.ascontiguousarray(np.asarray(indices, dtype=np.int64))
+    out = np.zeros((len(idx), n * n), dtype=np.uint8)
+    tot = ctypes.c_int64(0)
+    _check(_lib.dls_split_sample(n, flags, depth,
+                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(idx),
+                                 _u8(out), ctypes.byref(tot)), "dls_split_sample")
+    return out, int(tot.value)
+
+
+def dls_group_order(n: int) -> int:
+    r = _lib.dls_group_order(n)
+    if r < 0:
+        raise DLSError(int(r), "dls_group_order")
+    return int(r)
+
+
+def dls_canon(n: int, h) -> int:
+    m = ctypes.c_uint32(0)
+    _check(_lib.dls_canon(n, _u8(_square(n, h)), ctypes.byref(m)), "dls_canon")
+    return int(m.value)
+
+
+def dls_count(n: int, flags: int, prefixes) -> np.ndarray:
+    """Exact per-prefix counts on the GPU (host buffers, blocking)."""
+    p = np.ascontiguousarray(np.asarray(prefixes, dtype=np.uint8).reshape(-1, n * n))
+    out = np.zeros(p.shape[0], dtype=np.uint64)
+    if p.shape[0]:
+        _check(_lib.dls_count(n, flags, _u8(p), p.shape[0],
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), "dls_count")
+    return out
+
+
+def _pattern(n: int, pattern) -> Optional[np.ndarray]:
+    if pattern is None:
+        return None
+    return _square(n, np.asarray(pattern).astype(bool).astype(np.uint8))
+
+
+def _launch(launch) -> Optional[DlsLaunch]:
+    if launch is None:
+        return None
+    if isinstance(launch, DlsLaunch):
+        return launch
+    return DlsLaunch(**launch)
+
+
+def dls_count_async(n: int, flags: int, pattern, d_prefixes, num: int, d_counts,
+                    d_status=None, stream=None) -> None:
+    pat = _pattern(n, pattern)
+    _check(_lib.dls_count_async(n, flags, None if pat is None else _u8(pat), _ptr(d_prefixes),
+                                num, _ptr(d_counts), _ptr(d_status), _stream(stream)),
+           "dls_count_async")
+
+
+def dls_count_async_ex(n: int, flags: int, pattern, d_prefixes, num: int, d_counts,
+                       d_status=None, stream=None, launch=None) -> None:
+    pat = _pattern(n, pattern)
+    lc = _launch(launch)
+    _check(_lib.dls_count_async_ex(n, flags, None if pat is None else _u8(pat), _ptr(d_prefixes),
+                                   num, _ptr(d_counts), _ptr(d_status), _stream(stream),
+                                   None if lc is None else ctypes.byref(lc)),
+           "dls_count_async_ex")
+
+
+def dls_count_async_stats(n: int, flags: int, pattern, d_prefixes, num: int, d_counts,
+                          d_status=None, stream=None, launch=None, d_steps=None) -> None:
+    pat = _pattern(n, pattern)
+    lc = _launch(launch)
+    _check(_lib.dls_count_async_stats(n, flags, None if pat is None else _u8(pat),
+                                      _ptr(d_prefixes), num, _ptr(d_counts), _ptr(d_status),
+                                      _stream(stream), None if lc is None else ctypes.byref(lc),
+                                      _ptr(d_steps)), "dls_count_async_stats")
+
+
+def dls_valu_probe(blocks: int, iters: int, d_sink, stream=None) -> None:
+    _check(_lib.dls_valu_probe(blocks, iters, _ptr(d_sink), _stream(stream)), "dls_valu_probe")

@@ -1,0 +1,419 @@
+// dls_api.cpp -- the C ABI declared in include/dls.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dls.h"
+#include "dls_host.hpp"
+#include "dls_kernels.hpp"
+
+namespace {
+
+using dls::kEmpty;
+
+bool valid_n(int n) { return n >= 1 && n <= DLS_MAXN; }
+
+bool valid_cells(int n, const uint8_t *sq) {
+    for (int c = 0; c < n * n; ++c)
+        if (sq[c] != kEmpty && sq[c] >= n) return false;
+    return true;
+}
+
+std::vector<uint8_t> identity_prefix(int n) {
+    std::vector<uint8_t> p((size_t)n * n, kEmpty);
+    for (int j = 0; j < n; ++j) p[j] = (uint8_t)j;
+    return p;
+}
+
+std::vector<uint8_t> pattern_of(int n, const uint8_t *sq) {
+    std::vector<uint8_t> a((size_t)n * n);
+    for (int c = 0; c < n * n; ++c) a[c] = sq[c] != kEmpty;
+    return a;
+}
+
+// hourglass cells that the order lists (left-half representatives with VS)
+int hourglass_levels(int n, bool vs, const std::vector<int> &order) {
+    std::vector<uint8_t> in((size_t)n * n, 0);
+    for (int c : dls::hourglass_cells(n)) in[c] = 1;
+    int k = 0;
+    for (int c : order) {
+        int i = c / n, j = c % n;
+        if (in[c] || (vs && in[i * n + (n - 1 - j)])) ++k;
+    }
+    return k;
+}
+
+bool make_spec(int n, uint32_t flags, const uint8_t *base, int depth, dls::SplitSpec &spec,
+               std::unique_ptr<dls::HourglassGroup> &group) {
+    const bool vs = flags & DLS_VSYM;
+    std::vector<uint8_t> assigned = pattern_of(n, base);
+    std::vector<int> first;
+    if (flags & DLS_SYMBREAK) first = dls::hourglass_cells(n);
+    std::vector<int> order = dls::fill_order(n, vs, assigned.data(), first);
+    if (depth < 0 || depth > (int)order.size()) return false;
+    spec.n = n;
+    spec.vs = vs;
+    spec.cells.assign(order.begin(), order.begin() + depth);
+    spec.group = nullptr;
+    spec.hg_level = -1;
+    if (flags & DLS_SYMBREAK) {
+        int hl = hourglass_levels(n, vs, order);
+        if (depth < hl || n < 2) return false;
+        group.reset(new dls::HourglassGroup(n));
+        spec.group = group.get();
+        spec.hg_level = hl;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// device resources
+// ---------------------------------------------------------------------------
+
+struct QueueSlot {
+    dlsk::Ctrl *ctrl = nullptr;
+    dlsk::Item *items = nullptr;
+    int64_t cap = 0;
+};
+
+struct DeviceState {
+    bool init = false;
+    int cus = 0;
+    std::map<void *, QueueSlot> slots;  // one work queue per stream
+};
+
+std::mutex g_dev_mu;
+std::map<int, DeviceState> g_dev;
+
+constexpr int64_t kItemCap = 1 << 18;
+
+int device_state(DeviceState **out, int *dev_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLS_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceState &ds = g_dev[dev];
+    if (!ds.init) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DLS_EDEVICE;
+        ds.cus = prop.multiProcessorCount;
+        ds.init = true;
+    }
+    *out = &ds;
+    *dev_out = dev;
+    return DLS_OK;
+}
+
+int queue_slot(DeviceState *ds, void *stream, QueueSlot **out) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = ds->slots.find(stream);
+    if (it == ds->slots.end()) {
+        QueueSlot s;
+        if (hipMalloc((void **)&s.ctrl, sizeof(dlsk::Ctrl)) != hipSuccess) return DLS_ENOMEM;
+        if (hipMalloc((void **)&s.items, sizeof(dlsk::Item) * kItemCap) != hipSuccess) {
+            (void)hipFree(s.ctrl);
+            return DLS_ENOMEM;
+        }
+        s.cap = kItemCap;
+        if (hipMemset(s.ctrl, 0, sizeof(dlsk::Ctrl)) != hipSuccess ||
+            hipMemset(s.items, 0, sizeof(dlsk::Item) * kItemCap) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            return DLS_EDEVICE;
+        it = ds->slots.emplace(stream, s).first;
+    }
+    *out = &it->second;
+    return DLS_OK;
+}
+
+int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan) {
+    std::vector<uint8_t> pat((size_t)n * n, 0);
+    if (pattern) {
+        for (int c = 0; c < n * n; ++c) pat[c] = pattern[c] ? 1 : 0;
+    } else {
+        for (int j = 0; j < n; ++j) pat[j] = 1;
+    }
+    if (vs)
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                if (pat[i * n + j] != pat[i * n + (n - 1 - j)]) return DLS_EINVAL;
+    std::vector<int> order = dls::fill_order(n, vs, pat.data(), {});
+    if ((int)order.size() > dlsk::kMaxLevels) return DLS_EINVAL;
+    std::memset(&plan, 0, sizeof(plan));
+    plan.nlev = (int)order.size();
+    for (int k = 0; k < plan.nlev; ++k) plan.desc[k] = dlsk::make_desc(n, order[k] / n, order[k] % n);
+    for (int c = 0; c < n * n; ++c)
+        if (pat[c]) plan.patbits[c >> 5] |= 1u << (c & 31);
+    return DLS_OK;
+}
+
+int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,
+                     uint64_t *d_counts, uint32_t *d_status, void *stream, const dls_launch *launch,
+                     uint64_t *d_steps) {
+    if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
+    if (num > 0 && (!d_prefixes || !d_counts)) return DLS_EINVAL;
+    if (num == 0) return DLS_OK;
+    const bool vs = flags & DLS_VSYM;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds = nullptr;
+    int dev = 0;
+    int rc = device_state(&ds, &dev);
+    if (rc) return rc;
+    if (vs && n % 2 == 1 && n > 1) {
+        // no vertically symmetric square of odd order > 1 exists
+        return hipMemsetAsync(d_counts, 0, sizeof(uint64_t) * num, st) == hipSuccess ? DLS_OK : DLS_EDEVICE;
+    }
+    dlsk::LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    rc = build_plan(n, vs, pattern, a.plan);
+    if (rc) return rc;
+    a.n = n;
+    a.vs = vs;
+    a.persistent = !(flags & DLS_PLAIN);
+    a.prefixes = d_prefixes;
+    a.num = num;
+    a.counts = d_counts;
+    a.status = d_status;
+    a.steps = d_steps;
+    a.stream = st;
+    int block = (launch && launch->block) ? launch->block : 256;
+    if (block < 64 || block > 1024 || block % 64) return DLS_EINVAL;
+    while (block > 64 && dlsk::lds_bytes(n, a.plan.nlev, block) > 64 * 1024) block /= 2;
+    if (dlsk::lds_bytes(n, a.plan.nlev, block) > 64 * 1024) return DLS_EINVAL;
+    a.block = block;
+    if (a.persistent) {
+        QueueSlot *qs = nullptr;
+        rc = queue_slot(ds, stream, &qs);
+        if (rc) return rc;
+        a.ctrl = qs->ctrl;
+        a.items = qs->items;
+        a.item_cap = (a.plan.nlev <= dlsk::kItemMaxLevels) ? qs->cap : 0;
+        int bpc = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 2048 / block;
+        if (bpc < 1) bpc = 1;
+        a.grid = ds->cus * bpc;
+        a.tune.refill_every = (launch && launch->refill_every) ? launch->refill_every : 32;
+        a.tune.steal_depth = (launch && launch->steal_depth) ? launch->steal_depth : std::max(4, n);
+        a.tune.low_water = 2 * ds->cus * 64;
+    }
+    return dlsk::launch(a) == hipSuccess ? DLS_OK : DLS_EDEVICE;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *dls_strerror(int err) {
+    switch (err) {
+        case DLS_OK: return "ok";
+        case DLS_EINVAL: return "invalid argument";
+        case DLS_ERANGE: return "output capacity too small";
+        case DLS_ENOMEM: return "out of memory";
+        case DLS_EDEVICE: return "HIP device error";
+        case DLS_EPATTERN: return "prefix does not match the pattern";
+        default: return "unknown error";
+    }
+}
+
+const char *dls_version(void) { return "dls-mi355x 1.0 (gfx950)"; }
+
+int dls_order(int n, uint32_t flags, const uint8_t *assigned, uint8_t *order_out, int *len_out) {
+    if (!valid_n(n) || !assigned || !order_out || !len_out) return DLS_EINVAL;
+    if (flags & ~(uint32_t)(DLS_VSYM | DLS_SYMBREAK)) return DLS_EINVAL;
+    try {
+        std::vector<int> first;
+        if (flags & DLS_SYMBREAK) first = dls::hourglass_cells(n);
+        std::vector<int> o = dls::fill_order(n, flags & DLS_VSYM, assigned, first);
+        for (size_t k = 0; k < o.size(); ++k) order_out[k] = (uint8_t)o[k];
+        *len_out = (int)o.size();
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int dls_split(int n, uint32_t flags, int depth, uint8_t *prefixes_out, uint32_t *mult_out, int64_t cap,
+              int64_t *num_out) {
+    if (!valid_n(n) || !num_out || (flags & ~(uint32_t)(DLS_VSYM | DLS_SYMBREAK))) return DLS_EINVAL;
+    try {
+        std::vector<uint8_t> base = identity_prefix(n);
+        dls::SplitSpec spec;
+        std::unique_ptr<dls::HourglassGroup> group;
+        if (!make_spec(n, flags, base.data(), depth, spec, group)) return DLS_EINVAL;
+        if (!prefixes_out) {
+            *num_out = dls::split_count(spec, base.data());
+            return DLS_OK;
+        }
+        const int64_t total = dls::split_write(spec, base.data(), prefixes_out, mult_out, cap);
+        *num_out = total;
+        if (total > cap) return DLS_ERANGE;
+        if (mult_out && !(flags & DLS_SYMBREAK)) std::fill(mult_out, mult_out + total, 1u);
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int dls_split_from(int n, uint32_t flags, const uint8_t *base, int depth, uint8_t *prefixes_out, int64_t cap,
+                   int64_t *num_out) {
+    if (!valid_n(n) || !base || !num_out || (flags & ~(uint32_t)DLS_VSYM)) return DLS_EINVAL;
+    if (!valid_cells(n, base)) return DLS_EINVAL;
+    try {
+        std::vector<uint8_t> b(base, base + n * n);
+        if (flags & DLS_VSYM) {
+            if (!dls::vs_complete(n, base, b.data())) {
+                *num_out = 0;
+                return DLS_OK;
+            }
+        }
+        dls::SplitSpec spec;
+        std::unique_ptr<dls::HourglassGroup> group;
+        if (!make_spec(n, flags, b.data(), depth, spec, group)) return DLS_EINVAL;
+        if (!prefixes_out) {
+            *num_out = dls::split_count(spec, b.data());
+            return DLS_OK;
+        }
+        int64_t total = dls::split_write(spec, b.data(), prefixes_out, nullptr, cap);
+        *num_out = total;
+        if (total > cap) return DLS_ERANGE;
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int dls_split_sample(int n, uint32_t flags, int depth, const int64_t *indices, int64_t k,
+                     uint8_t *prefixes_out, int64_t *total_out) {
+    if (!valid_n(n) || !total_out || k < 0 || (k > 0 && (!indices || !prefixes_out))) return DLS_EINVAL;
+    if (flags & ~(uint32_t)DLS_VSYM) return DLS_EINVAL;
+    for (int64_t t = 0; t < k; ++t)
+        if (indices[t] < 0 || (t > 0 && indices[t] <= indices[t - 1])) return DLS_EINVAL;
+    try {
+        std::vector<uint8_t> base = identity_prefix(n);
+        dls::SplitSpec spec;
+        std::unique_ptr<dls::HourglassGroup> group;
+        if (!make_spec(n, flags, base.data(), depth, spec, group)) return DLS_EINVAL;
+        int64_t r = dls::split_select(spec, base.data(), indices, k, prefixes_out);
+        if (r < 0) {
+            *total_out = -r - 1;
+            return DLS_ERANGE;
+        }
+        *total_out = r;
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int64_t dls_group_order(int n) {
+    if (n < 2 || n > DLS_MAXN) return DLS_EINVAL;
+    int64_t m = n / 2, r = 2;
+    for (int64_t k = 0; k < m; ++k) r *= 2;
+    for (int64_t k = 2; k < m; ++k) r *= k;
+    return r;
+}
+
+int dls_canon(int n, const uint8_t *h, uint32_t *mult_out) {
+    if (n < 2 || n > DLS_MAXN || !h || !mult_out || !valid_cells(n, h)) return DLS_EINVAL;
+    for (int c : dls::hourglass_cells(n))
+        if (h[c] == kEmpty) return DLS_EINVAL;
+    for (int j = 0; j < n; ++j)
+        if (h[j] != j) return DLS_EINVAL;
+    try {
+        dls::HourglassGroup g(n);
+        *mult_out = g.canon(h);
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int dls_count_async(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,
+                    uint64_t *d_counts, uint32_t *d_status, void *stream) {
+    return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, nullptr, nullptr);
+}
+
+int dls_count_async_ex(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,
+                       uint64_t *d_counts, uint32_t *d_status, void *stream, const dls_launch *launch) {
+    return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, launch, nullptr);
+}
+
+int dls_count_async_stats(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,
+                          uint64_t *d_counts, uint32_t *d_status, void *stream, const dls_launch *launch,
+                          uint64_t *d_steps) {
+    return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, launch, d_steps);
+}
+
+int dls_count(int n, uint32_t flags, const uint8_t *prefixes, int64_t num, uint64_t *counts_out) {
+    if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
+    if (num > 0 && (!prefixes || !counts_out)) return DLS_EINVAL;
+    const int nn = n * n;
+    for (int64_t k = 0; k < num; ++k)
+        if (!valid_cells(n, prefixes + k * nn)) return DLS_EINVAL;
+    if (num == 0) return DLS_OK;
+    const bool vs = flags & DLS_VSYM;
+    std::fill(counts_out, counts_out + num, 0);
+    if (vs && n % 2 == 1 && n > 1) return DLS_OK;
+    try {
+        // group prefixes by which cells they assign (mirror-completed with VS)
+        std::map<std::vector<uint8_t>, std::vector<int64_t>> groups;
+        std::vector<uint8_t> work((size_t)num * nn);
+        for (int64_t k = 0; k < num; ++k) {
+            uint8_t *dst = work.data() + k * nn;
+            if (vs) {
+                if (!dls::vs_complete(n, prefixes + k * nn, dst)) continue;  // count stays 0
+            } else {
+                std::memcpy(dst, prefixes + k * nn, nn);
+            }
+            groups[pattern_of(n, dst)].push_back(k);
+        }
+        hipStream_t st = nullptr;
+        for (auto &g : groups) {
+            const std::vector<int64_t> &ids = g.second;
+            const int64_t m = (int64_t)ids.size();
+            std::vector<uint8_t> packed((size_t)m * nn);
+            for (int64_t t = 0; t < m; ++t) std::memcpy(packed.data() + t * nn, work.data() + ids[t] * nn, nn);
+            DevBuf dp, dc, dsb;
+            if (hipMalloc(&dp.p, packed.size()) != hipSuccess) return DLS_ENOMEM;
+            if (hipMalloc(&dc.p, sizeof(uint64_t) * m) != hipSuccess) return DLS_ENOMEM;
+            if (hipMalloc(&dsb.p, sizeof(uint32_t)) != hipSuccess) return DLS_ENOMEM;
+            if (hipMemcpy(dp.p, packed.data(), packed.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemset(dsb.p, 0, sizeof(uint32_t)) != hipSuccess)
+                return DLS_EDEVICE;
+            int rc = count_async_impl(n, flags, g.first.data(), (const uint8_t *)dp.p, m, (uint64_t *)dc.p,
+                                      (uint32_t *)dsb.p, st, nullptr, nullptr);
+            if (rc) return rc;
+            std::vector<uint64_t> c((size_t)m);
+            uint32_t status = 0;
+            if (hipStreamSynchronize(st) != hipSuccess ||
+                hipMemcpy(c.data(), dc.p, sizeof(uint64_t) * m, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(&status, dsb.p, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+                return DLS_EDEVICE;
+            if (status & 2u) return DLS_EDEVICE;
+            if (status & 1u) return DLS_EPATTERN;
+            for (int64_t t = 0; t < m; ++t) counts_out[ids[t]] = c[t];
+        }
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream) {
+    if (blocks < 1 || iters < 0 || !d_sink) return DLS_EINVAL;
+    return dlsk::launch_valu_probe(blocks, iters, d_sink, (hipStream_t)stream) == hipSuccess ? DLS_OK
+                                                                                             : DLS_EDEVICE;
+}
+
+}  // extern "C"
