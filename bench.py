@@ -1,0 +1,245 @@
+"""Benchmark: order-8 diagonal Latin squares enumerated per second on one
+MI355X, persistent batched kernel vs plain kernel, exact counts.
+
+Workload (one "step"): every workunit of the order-8 count with symmetry
+breaking -- first row fixed, canonical hourglass designs (Alg. 5-6) each
+extended by all consistent fillings of row 1 -- counted on the GPU, then the
+class-power-weighted total reduced on the device and checked against the
+paper's 7 447 587 840.  The prefixes are split once on the host and are
+resident in HBM when the timed region starts.
+
+Prints one JSON line (see the field list at the bottom)."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "order-8 DLS enumerated/sec (exact counts), persistent batched vs plain kernel"
+ORDER8_FIXED = 7447587840            # paper Sec. 5.1
+# MI355X integer VALU: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one 32-bit op per lane-cycle
+INT_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12
+COPY_BYTES = 256 << 20          # calibration copy for the HBM byte counters
+# algorithmic integer ops of Alg. 4 per unit (the per-unit model of the roofline):
+# a cell entry costs 3 (OR of the masks, XOR with AllN, loop test), an
+# assignment 9 (isolate 2, mark 2, unmark 2, clear lowest 2, loop test 1).  One
+# downward DFS step is one assignment plus one cell entry; upward steps are
+# the unmark half already counted.  Every task start is one cell entry.
+OPS_PER_DOWN_STEP = 12
+OPS_PER_TASK = 3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sustained-steps", type=int, default=2,
+                    help="steps of the full order-8 count without symmetry breaking")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="a few persistent launches only (for rocprofv3 runs)")
+    return ap.parse_args()
+
+
+class Timer:
+    """Per-launch HIP event pairs on the stream the kernels run on."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream, self.pairs = torch, stream, []
+
+    def __enter__(self):
+        self.a = self.torch.cuda.Event(enable_timing=True)
+        self.b = self.torch.cuda.Event(enable_timing=True)
+        self.a.record(self.stream)
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record(self.stream)
+        self.pairs.append((self.a, self.b))
+
+    def mean_ms(self):
+        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs]))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the workunits would be sharded across GPUs by a host queue; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1709_02599_amd as dls
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n = 8
+
+    # ---------------- input: the symmetry-broken split (host, once) ----------------
+    t0 = time.perf_counter()
+    pre, mult = dls.dls_split(n, dls.DLS_SYMBREAK, 26)
+    split_s = time.perf_counter() - t0
+    num = len(pre)
+    pattern = (pre[0] != 0xFF).astype(np.uint8)
+    d_pre = torch.from_numpy(pre).to(dev)
+    d_mult = torch.from_numpy(mult.astype(np.int64)).to(dev)
+    d_cnt = torch.zeros(num, dtype=torch.int64, device=dev)
+    d_status = torch.zeros(1, dtype=torch.int32, device=dev)
+    d_steps = torch.zeros(1, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    def run(flags, launch=None):
+        dls.dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_status, stream, launch)
+        return (d_cnt * d_mult).sum()
+
+    # deterministic work measure: DFS steps of the whole batch (instrumented run)
+    dls.dls_count_async_stats(n, 0, pattern, d_pre, num, d_cnt, d_status, stream, None, d_steps)
+    torch.cuda.synchronize()
+    total_steps = int(d_steps.item())
+    leaves = int(d_cnt.sum().item())
+    weighted = int((d_cnt * d_mult).sum().item())
+    assert weighted == ORDER8_FIXED, weighted
+    alg_ops = OPS_PER_DOWN_STEP * (total_steps // 2) + OPS_PER_TASK * num
+
+    if args.profile_only:
+        # a few launches of each kernel, plus a device-to-device copy of known
+        # size whose counter readings calibrate FETCH_SIZE / WRITE_SIZE
+        for _ in range(3):
+            run(0)
+        for _ in range(3):
+            run(dls.DLS_PLAIN)
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only": True, "prefixes": num, "steps": total_steps,
+                          "copy_bytes": COPY_BYTES}))
+        return
+
+    results = {}
+    for name, flags in (("persistent", 0), ("plain", dls.DLS_PLAIN)):
+        for _ in range(args.warmup):
+            run(flags)
+        torch.cuda.synchronize()
+        timer = Timer(torch, stream)
+        t_start = time.perf_counter()
+        tot = None
+        for _ in range(args.steps):
+            with timer:
+                tot = run(flags)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        st = int(d_status.item())
+        ok = int(tot.item()) == ORDER8_FIXED and st == 0
+        results[name] = {"ms_per_step": 1e3 * wall / args.steps, "kernel_ms": timer.mean_ms(),
+                         "exact": ok}
+
+    # ---------------- sustained variant: the full count, no symmetry breaking ----------------
+    sustained = None
+    if args.sustained_steps > 0:
+        spre, _ = dls.dls_split(n, 0, 14)
+        spat = (spre[0] != 0xFF).astype(np.uint8)
+        sd_pre = torch.from_numpy(spre).to(dev)
+        sd_cnt = torch.zeros(len(spre), dtype=torch.int64, device=dev)
+        sustained = {"prefixes": len(spre), "leaves": ORDER8_FIXED}
+        for name, flags in (("persistent", 0), ("plain", dls.DLS_PLAIN)):
+            dls.dls_count_async(n, flags, spat, sd_pre, len(spre), sd_cnt, d_status, stream)
+            torch.cuda.synchronize()
+            timer = Timer(torch, stream)
+            for _ in range(args.sustained_steps):
+                with timer:
+                    dls.dls_count_async(n, flags, spat, sd_pre, len(spre), sd_cnt, d_status, stream)
+            s = sd_cnt.sum()
+            torch.cuda.synchronize()
+            ms = timer.mean_ms()
+            sustained[name] = {"kernel_ms": ms, "dls_per_s": ORDER8_FIXED / (ms * 1e-3),
+                               "exact": int(s.item()) == ORDER8_FIXED}
+        del sd_pre, sd_cnt
+
+    # ---------------- CPU oracle on a bounded sample of the same workload ----------------
+    # The oracle builds its own sample: seeded canonical hourglasses (its own
+    # classes), each extended by every filling of row 1 along its own order.
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        from paper_1709_02599_amd import workloads
+        threads = oracle.default_threads()
+        _, reps, _ = oracle.hourglass_classes(n, threads=threads)
+        hc = oracle.hourglass_cells(n)
+        order = oracle.fill_order(n, first=hc)
+        hl = len([c for c in order if c in set(hc)])
+
+        def sample(k):
+            pick = workloads.sample_positions(len(reps), k, seed=2)
+            return np.concatenate([oracle.assignments(n, reps[i], order[hl:hl + 6]) for i in pick])
+
+        k = 1000
+        while True:
+            spl = sample(k)
+            t0 = time.perf_counter()
+            oc = oracle.count_many(n, spl, threads=threads)
+            dt = time.perf_counter() - t0
+            if dt > args.cpu_seconds / 3 or k >= len(reps):
+                break
+            k = min(len(reps), int(k * min(20.0, args.cpu_seconds / max(dt, 1e-3))))
+        cpu = {"value": float(oc.sum()) / dt, "unit": "DLS/s", "cores": threads, "kind": "oracle",
+               "sample": f"{k} seeded canonical hourglasses of {len(reps)} with all row-1 "
+                         f"fillings ({len(spl)} prefixes, {int(oc.sum())} squares), "
+                         f"{dt:.1f} s on {threads} threads",
+               "seconds": dt}
+
+    p = results["persistent"]
+    value = leaves / (p["ms_per_step"] * 1e-3)
+    kernel_s = p["kernel_ms"] * 1e-3
+    achieved = alg_ops / kernel_s
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DLS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": p["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "order-8 DLS, first row fixed, canonical hourglass symmetry "
+                               "breaking, split at hourglass + row 1",
+                   "order": n, "prefixes": num, "leaves_per_step": leaves,
+                   "weighted_total": weighted, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": None},
+        "cpu_baseline": cpu,
+        "plain_kernel": {"value": leaves / (results["plain"]["ms_per_step"] * 1e-3),
+                         "ms_per_step": results["plain"]["ms_per_step"],
+                         "kernel_ms": results["plain"]["kernel_ms"]},
+        "persistent_kernel_ms": p["kernel_ms"],
+        "speedup_persistent_vs_plain": results["plain"]["ms_per_step"] / p["ms_per_step"],
+        "effective_counted_per_s": weighted / (p["ms_per_step"] * 1e-3),
+        "dfs_steps_per_launch": total_steps,
+        "alg_ops_per_launch": alg_ops,
+        "split_seconds_host": split_s,
+        "sustained_full_count": sustained,
+        "exact": all(r["exact"] for r in results.values()),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -60,6 +60,10 @@ const char *dls_strerror(int err);
 /* Library version string, e.g. "dls-mi355x 1.0 (gfx950)". */
 const char *dls_version(void);
 
+/* Name and text of the last HIP runtime error that made a call on this
+ * thread return DLS_EDEVICE ("" if none).  Diagnostics only. */
+const char *dls_last_hip_error(void);
+
 /*
  * Fill order of the empty cells (Sec. 2.3, Fig. 1).  Starting from the
  * assigned cells (assigned[c] != 0 for c in 0..n*n-1), repeatedly: if a row,
@@ -133,7 +137,10 @@ int dls_count(int n, uint32_t flags, const uint8_t *prefixes, int64_t num,
 typedef struct {
     int block;          /* threads per workgroup (64..1024, multiple of 64)   */
     int blocks_per_cu;  /* persistent kernel: resident workgroups per CU      */
-    int steal_depth;    /* persistent kernel: donate only levels < end-this   */
+    int steal_depth;    /* persistent kernel: give subtrees to idle waves on
+                           other CUs only from levels < (levels - steal_depth);
+                           0 = library default (on for batches too small to
+                           fill the GPU), negative = off                       */
     int refill_every;   /* persistent kernel: DFS steps between refills       */
 } dls_launch;
 

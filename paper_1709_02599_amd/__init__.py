@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "DLS_VSYM", "DLS_SYMBREAK", "DLS_PLAIN", "DLS_EMPTY", "DLSError", "LIB_PATH",
-    "dls_version", "dls_strerror", "dls_order", "dls_split", "dls_split_from",
+    "dls_version", "dls_strerror", "dls_last_hip_error", "dls_order", "dls_split", "dls_split_from",
     "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async",
     "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
 ]
@@ -32,7 +32,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdls.so")
 
 class DLSError(RuntimeError):
     def __init__(self, code: int, what: str):
-        super().__init__(f"{what}: {dls_strerror(code)} ({code})")
+        detail = _lib.dls_last_hip_error().decode() if code == -4 else ""
+        super().__init__(f"{what}: {dls_strerror(code)} ({code}) {detail}".rstrip())
         self.code = code
 
 
@@ -42,6 +43,14 @@ class DlsLaunch(ctypes.Structure):
 
 
 def _load() -> ctypes.CDLL:
+    # torch ships its own HIP runtime under the same soname as the system's.
+    # Loading torch first makes libdls.so bind to that already-loaded runtime;
+    # the other order would put two HIP runtimes in one process, and device
+    # pointers from torch would be foreign to the library's runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(hipcc, gfx950) before using paper_1709_02599_amd")
@@ -53,6 +62,7 @@ def _load() -> ctypes.CDLL:
     sig = {
         "dls_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "dls_version": (ctypes.c_char_p, []),
+        "dls_last_hip_error": (ctypes.c_char_p, []),
         "dls_order": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, u8p,
                                      ctypes.POINTER(ctypes.c_int)]),
         "dls_split": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.c_int, u8p, u32p,
@@ -121,6 +131,10 @@ def dls_strerror(code: int) -> str:
 
 def dls_version() -> str:
     return _lib.dls_version().decode()
+
+
+def dls_last_hip_error() -> str:
+    return _lib.dls_last_hip_error().decode()
 
 
 def dls_order(n: int, flags: int = 0, assigned=None) -> list:

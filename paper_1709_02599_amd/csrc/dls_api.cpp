@@ -79,29 +79,43 @@ bool make_spec(int n, uint32_t flags, const uint8_t *base, int depth, dls::Split
 
 struct QueueSlot {
     dlsk::Ctrl *ctrl = nullptr;
-    dlsk::Item *items = nullptr;
+    void *items = nullptr;      // donated task records (kItemCap of the largest size)
+    uint32_t *ready = nullptr;  // publication flag per donated slot
     int64_t cap = 0;
+    void *records = nullptr;    // task records of the batch in flight on this stream
+    size_t records_bytes = 0;
 };
 
 struct DeviceState {
     bool init = false;
     int cus = 0;
-    std::map<void *, QueueSlot> slots;  // one work queue per stream
+    std::map<void *, QueueSlot> slots;  // scratch and work queue per stream
 };
 
 std::mutex g_dev_mu;
 std::map<int, DeviceState> g_dev;
+thread_local std::string g_last_hip;
+
+int hip_fail(hipError_t e, int code) {
+    g_last_hip = hipGetErrorName(e);
+    g_last_hip += ": ";
+    g_last_hip += hipGetErrorString(e);
+    return code;
+}
 
 constexpr int64_t kItemCap = 1 << 18;
+constexpr size_t kMaxRecord = 80;  // largest task record (order 16)
 
 int device_state(DeviceState **out, int *dev_out) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return DLS_EDEVICE;
+    hipError_t e0 = hipGetDevice(&dev);
+    if (e0 != hipSuccess) return hip_fail(e0, DLS_EDEVICE);
     std::lock_guard<std::mutex> lk(g_dev_mu);
     DeviceState &ds = g_dev[dev];
     if (!ds.init) {
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DLS_EDEVICE;
+        hipError_t e1 = hipGetDeviceProperties(&prop, dev);
+        if (e1 != hipSuccess) return hip_fail(e1, DLS_EDEVICE);
         ds.cus = prop.multiProcessorCount;
         ds.init = true;
     }
@@ -110,24 +124,38 @@ int device_state(DeviceState **out, int *dev_out) {
     return DLS_OK;
 }
 
-int queue_slot(DeviceState *ds, void *stream, QueueSlot **out) {
+// Scratch for one stream: work-queue control block, donated-record slots and
+// their flags (allocated once), task records (grown to the largest batch).
+int queue_slot(DeviceState *ds, void *stream, size_t records_bytes, QueueSlot **out) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     auto it = ds->slots.find(stream);
     if (it == ds->slots.end()) {
         QueueSlot s;
         if (hipMalloc((void **)&s.ctrl, sizeof(dlsk::Ctrl)) != hipSuccess) return DLS_ENOMEM;
-        if (hipMalloc((void **)&s.items, sizeof(dlsk::Item) * kItemCap) != hipSuccess) {
-            (void)hipFree(s.ctrl);
-            return DLS_ENOMEM;
-        }
+        if (hipMalloc(&s.items, kMaxRecord * kItemCap) != hipSuccess) return DLS_ENOMEM;
+        if (hipMalloc((void **)&s.ready, sizeof(uint32_t) * kItemCap) != hipSuccess) return DLS_ENOMEM;
         s.cap = kItemCap;
-        if (hipMemset(s.ctrl, 0, sizeof(dlsk::Ctrl)) != hipSuccess ||
-            hipMemset(s.items, 0, sizeof(dlsk::Item) * kItemCap) != hipSuccess ||
-            hipDeviceSynchronize() != hipSuccess)
-            return DLS_EDEVICE;
+        hipError_t e2 = hipMemset(s.ctrl, 0, sizeof(dlsk::Ctrl));
+        if (e2 == hipSuccess) e2 = hipMemset(s.ready, 0, sizeof(uint32_t) * kItemCap);
+        if (e2 == hipSuccess) e2 = hipDeviceSynchronize();
+        if (e2 != hipSuccess) return hip_fail(e2, DLS_EDEVICE);
         it = ds->slots.emplace(stream, s).first;
     }
-    *out = &it->second;
+    QueueSlot &q = it->second;
+    if (q.records_bytes < records_bytes) {
+        if (q.records) {
+            // the previous batch on this stream may still be running
+            hipError_t e3 = hipStreamSynchronize((hipStream_t)stream);
+            if (e3 != hipSuccess) return hip_fail(e3, DLS_EDEVICE);
+            (void)hipFree(q.records);
+            q.records = nullptr;
+            q.records_bytes = 0;
+        }
+        size_t want = records_bytes + records_bytes / 4;
+        if (hipMalloc(&q.records, want) != hipSuccess) return DLS_ENOMEM;
+        q.records_bytes = want;
+    }
+    *out = &q;
     return DLS_OK;
 }
 
@@ -146,7 +174,7 @@ int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan) {
     if ((int)order.size() > dlsk::kMaxLevels) return DLS_EINVAL;
     std::memset(&plan, 0, sizeof(plan));
     plan.nlev = (int)order.size();
-    for (int k = 0; k < plan.nlev; ++k) plan.desc[k] = dlsk::make_desc(n, order[k] / n, order[k] % n);
+    for (int k = 0; k < plan.nlev; ++k) plan.desc[k] = dlsk::make_desc(n, vs, order[k] / n, order[k] % n);
     for (int c = 0; c < n * n; ++c)
         if (pat[c]) plan.patbits[c >> 5] |= 1u << (c & 31);
     return DLS_OK;
@@ -166,7 +194,8 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     if (rc) return rc;
     if (vs && n % 2 == 1 && n > 1) {
         // no vertically symmetric square of odd order > 1 exists
-        return hipMemsetAsync(d_counts, 0, sizeof(uint64_t) * num, st) == hipSuccess ? DLS_OK : DLS_EDEVICE;
+        hipError_t ez = dlsk::launch_zero(d_counts, num, st);
+        return ez == hipSuccess ? DLS_OK : hip_fail(ez, DLS_EDEVICE);
     }
     dlsk::LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -183,24 +212,36 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     a.stream = st;
     int block = (launch && launch->block) ? launch->block : 256;
     if (block < 64 || block > 1024 || block % 64) return DLS_EINVAL;
-    while (block > 64 && dlsk::lds_bytes(n, a.plan.nlev, block) > 64 * 1024) block /= 2;
-    if (dlsk::lds_bytes(n, a.plan.nlev, block) > 64 * 1024) return DLS_EINVAL;
+    while (block > 64 && dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent) > 64 * 1024) block /= 2;
+    if (dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent) > 64 * 1024) return DLS_EINVAL;
     a.block = block;
+    QueueSlot *qs = nullptr;
+    rc = queue_slot(ds, stream, dlsk::record_bytes(n, vs) * (size_t)num, &qs);
+    if (rc) return rc;
+    a.records = qs->records;
     if (a.persistent) {
-        QueueSlot *qs = nullptr;
-        rc = queue_slot(ds, stream, &qs);
-        if (rc) return rc;
         a.ctrl = qs->ctrl;
         a.items = qs->items;
-        a.item_cap = (a.plan.nlev <= dlsk::kItemMaxLevels) ? qs->cap : 0;
+        a.ready = qs->ready;
+        a.item_cap = qs->cap;
         int bpc = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 2048 / block;
         if (bpc < 1) bpc = 1;
         a.grid = ds->cus * bpc;
         a.tune.refill_every = (launch && launch->refill_every) ? launch->refill_every : 32;
-        a.tune.steal_depth = (launch && launch->steal_depth) ? launch->steal_depth : std::max(4, n);
-        a.tune.low_water = 2 * ds->cus * 64;
+        // Work given away across the chip pays for fences; it only pays off when
+        // the batch is too small to keep every lane busy (e.g. one big prefix).
+        // Inside a wave, idle lanes always take work from busy ones.
+        const int64_t lanes = (int64_t)a.grid * block;
+        int sd = num < lanes / 4 ? std::max(8, a.plan.nlev / 3) : 0;
+        if (launch && launch->steal_depth) sd = launch->steal_depth < 0 ? 0 : launch->steal_depth;
+        a.tune.steal_depth = sd;
+        a.tune.refill_min = 8;
+        a.tune.donate_max = 2;
+        a.tune.donate_low = 256;
+        a.tune.tail_poll = 4;
     }
-    return dlsk::launch(a) == hipSuccess ? DLS_OK : DLS_EDEVICE;
+    hipError_t e = dlsk::launch(a);
+    return e == hipSuccess ? DLS_OK : hip_fail(e, DLS_EDEVICE);
 }
 
 struct DevBuf {
@@ -227,6 +268,8 @@ const char *dls_strerror(int err) {
 }
 
 const char *dls_version(void) { return "dls-mi355x 1.0 (gfx950)"; }
+
+const char *dls_last_hip_error(void) { return g_last_hip.c_str(); }
 
 int dls_order(int n, uint32_t flags, const uint8_t *assigned, uint8_t *order_out, int *len_out) {
     if (!valid_n(n) || !assigned || !order_out || !len_out) return DLS_EINVAL;

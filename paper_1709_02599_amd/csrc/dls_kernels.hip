@@ -8,17 +8,22 @@
 // order is not entered: its candidate count is added directly.
 //
 // GPU form of that loop:
-//  * the 2N+2 line masks live in VGPRs, packed floor(32/N) lines per word;
-//    the cell of the current level selects the word and shift (a per-level
-//    descriptor table in LDS, uniform for the whole launch);
+//  * the 2N+2 line masks live in VGPRs: row and column lines are N-bit fields
+//    packed floor(64/N) to a 64-bit word (all eight lines of one kind in one
+//    word up to N = 8); a per-level descriptor gives the bit offset of the
+//    cell's row and column field, so reading a line is one 64-bit shift and
+//    marking a value is one shift and an XOR;
 //  * the per-lane stack holds, per level, the candidate set at the time the
-//    level was left downwards (the taken value is its lowest bit); it is
-//    kept in LDS, one row per level, lanes side by side (conflict-free);
-//  * one DFS step is the same instruction stream for every lane: either go
-//    down one level (take the lowest candidate) or go up one level (clear the
-//    value taken there and resume with the remaining candidates).  Marking and
-//    clearing are both XOR, so both directions share one code path and lanes
-//    at different depths stay converged.
+//    level was left downwards (the taken value is its lowest bit); it lives
+//    in LDS, one row per level with the lanes of a workgroup side by side;
+//  * a DFS step is one instruction stream for every lane: go down one level
+//    (take the lowest candidate) or up one level (clear the value taken there
+//    and resume with the rest).  Marking and clearing are both XOR, so lanes
+//    at different depths stay converged;
+//  * a prep kernel turns each prefix (n*n cells) into a task record: packed
+//    masks, level and candidate set.  The search kernels start tasks from
+//    records, and a lane that gives away part of its tree writes the same
+//    record (its masks rewound to the donated level).
 //
 // Vertical symmetry (Sec. 5.4): only the left half is searched; placing v at
 // (i,j) also places N-1-v at (i,N-1-j).  Row masks receive both values,
@@ -27,83 +32,89 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dls_kernels.hpp"
 
 namespace dlsk {
 
 // ---------------------------------------------------------------------------
-// geometry of the packed masks
+// geometry of the packed masks and task records
 // ---------------------------------------------------------------------------
 
-template <int N>
+template <int N, bool VS>
 struct Geo {
-    static constexpr int LPW = 32 / N;                 // lines per 32-bit word
-    static constexpr int W = (N + LPW - 1) / LPW;      // words per set of N lines
-    static constexpr uint32_t ALL = (N == 32) ? 0xFFFFFFFFu : ((1u << N) - 1u);
+    static constexpr int LPW = 64 / N;                        // lines per 64-bit word
+    static constexpr int NCOL = VS ? (N + 1) / 2 : N;         // column lines kept
+    static constexpr int WR = (N + LPW - 1) / LPW;            // words of row lines
+    static constexpr int WC = (NCOL + LPW - 1) / LPW;         // words of column lines
+    static constexpr uint32_t ALL = (1u << N) - 1u;
 };
 
-// descriptor fields (see make_desc on the host side)
-__device__ __forceinline__ uint32_t d_rsh(uint32_t d) { return d & 31u; }
-__device__ __forceinline__ uint32_t d_rw(uint32_t d) { return (d >> 5) & 7u; }
-__device__ __forceinline__ uint32_t d_csh(uint32_t d) { return (d >> 8) & 31u; }
-__device__ __forceinline__ uint32_t d_cw(uint32_t d) { return (d >> 13) & 7u; }
-__device__ __forceinline__ uint32_t d_md(uint32_t d) { return 0u - ((d >> 16) & 1u); }
-__device__ __forceinline__ uint32_t d_ad(uint32_t d) { return 0u - ((d >> 17) & 1u); }
+template <int N, bool VS>
+struct alignas(16) Rec {
+    uint64_t R[Geo<N, VS>::WR];
+    uint64_t C[Geo<N, VS>::WC];
+    uint32_t diag;    // md | ad << 16
+    uint32_t cl;      // cand | level << 16; level kNone: nothing to search
+    uint32_t origin;  // index of the prefix this task belongs to
+    uint32_t pad;
+};
+constexpr uint32_t kNone = 0xFFFFu;
 
 template <int W>
-__device__ __forceinline__ uint32_t pick(const uint32_t (&x)[W], uint32_t w) {
-    uint32_t r = x[0];
+__device__ __forceinline__ uint64_t pickw(const uint64_t (&x)[W], uint32_t w) {
+    uint64_t r = x[0];
 #pragma unroll
     for (int k = 1; k < W; ++k) r = (w == (uint32_t)k) ? x[k] : r;
     return r;
 }
 
 template <int W>
-__device__ __forceinline__ void flip(uint32_t (&x)[W], uint32_t w, uint32_t bits) {
+__device__ __forceinline__ void flipw(uint64_t (&x)[W], uint32_t w, uint64_t bits) {
+    if constexpr (W == 1) {
+        x[0] ^= bits;
+    } else {
 #pragma unroll
-    for (int k = 0; k < W; ++k) x[k] ^= (w == (uint32_t)k) ? bits : 0u;
+        for (int k = 0; k < W; ++k) x[k] ^= (w == (uint32_t)k) ? bits : 0ull;
+    }
 }
+
+__device__ __forceinline__ uint32_t d_rw(uint32_t d) { return (d >> 6) & 3u; }
+__device__ __forceinline__ uint32_t d_cw(uint32_t d) { return (d >> 14) & 3u; }
+__device__ __forceinline__ uint32_t d_md(uint32_t d) { return 0u - ((d >> 16) & 1u); }
+__device__ __forceinline__ uint32_t d_ad(uint32_t d) { return 0u - ((d >> 17) & 1u); }
 
 template <int N, bool VS>
 struct Lane {
-    static constexpr int W = Geo<N>::W;
-    uint32_t R[W];     // row masks
-    uint32_t C[W];     // column masks (left half only with VS)
-    uint32_t md, ad;   // diagonal masks
-    uint32_t cand;     // remaining candidates at the current level
-    uint32_t cur;      // descriptor of the current level's cell
-    int d;             // current level
-    int start;         // level at which this lane's task began
-    uint64_t cnt;      // completed squares found by this task
+    using G = Geo<N, VS>;
+    uint64_t R[G::WR];  // row lines
+    uint64_t C[G::WC];  // column lines (left half only with VS)
+    uint32_t md, ad;    // diagonal masks
+    uint32_t cand;      // remaining candidates at the current level
+    uint32_t cur;       // descriptor of the current level's cell
+    int d;              // current level
+    int start;          // level at which this task began
+    uint64_t cnt;       // squares completed by this task
 
-    __device__ __forceinline__ void clear() {
-#pragma unroll
-        for (int k = 0; k < W; ++k) R[k] = C[k] = 0u;
-        md = ad = 0u;
-        cnt = 0;
-    }
-
-    // forbidden values of the cell described by `desc`, as candidates
     __device__ __forceinline__ uint32_t cands(uint32_t desc) const {
-        uint32_t cr = pick<W>(R, d_rw(desc)) >> d_rsh(desc);
-        cr |= pick<W>(C, d_cw(desc)) >> d_csh(desc);
-        cr |= (md & d_md(desc)) | (ad & d_ad(desc));
-        return Geo<N>::ALL & ~cr;
+        const uint32_t r = (uint32_t)(pickw<G::WR>(R, d_rw(desc)) >> (desc & 63u));
+        const uint32_t c = (uint32_t)(pickw<G::WC>(C, d_cw(desc)) >> ((desc >> 8) & 63u));
+        return G::ALL & ~(r | c | (md & d_md(desc)) | (ad & d_ad(desc)));
     }
 
-    // mark (or clear: XOR) value bit b at the cell described by `desc`
+    // mark or clear (XOR) the value bit b at the cell of `desc`
     __device__ __forceinline__ void toggle(uint32_t desc, uint32_t b) {
         const uint32_t mdm = d_md(desc), adm = d_ad(desc);
         if constexpr (VS) {
-            // mirror value N-1-v of the lowest set bit v of b (b is one-hot or 0)
-            const uint32_t rb = b ? ((1u << (N - 1)) >> __builtin_ctz(b)) : 0u;
-            flip<W>(R, d_rw(desc), (b | rb) << d_rsh(desc));
-            flip<W>(C, d_cw(desc), b << d_csh(desc));
+            const uint32_t rb = (1u << (N - 1)) >> (__builtin_ctz(b) & 31u);  // N-1-v
+            flipw<G::WR>(R, d_rw(desc), (uint64_t)(b | rb) << (desc & 63u));
+            flipw<G::WC>(C, d_cw(desc), (uint64_t)b << ((desc >> 8) & 63u));
             md ^= (b & mdm) | (rb & adm);
             ad ^= (b & adm) | (rb & mdm);
         } else {
-            flip<W>(R, d_rw(desc), b << d_rsh(desc));
-            flip<W>(C, d_cw(desc), b << d_csh(desc));
+            flipw<G::WR>(R, d_rw(desc), (uint64_t)b << (desc & 63u));
+            flipw<G::WC>(C, d_cw(desc), (uint64_t)b << ((desc >> 8) & 63u));
             md ^= b & mdm;
             ad ^= b & adm;
         }
@@ -111,249 +122,442 @@ struct Lane {
 
     __device__ __forceinline__ bool done() const { return cand == 0u && d == start; }
 
-    // One DFS step.  Requires !done().  `desc`: per-level descriptors (LDS);
-    // `stk`: this lane's stack slot for level 0, levels `stride` apart.
+    // One DFS step; requires !done().  sdesc: level descriptors (LDS); the
+    // stack entry of level l sits at byte  lane_off + l * stride  of `lds`.
     template <class S>
-    __device__ __forceinline__ void step(const uint32_t *desc, S *stk, int stride, int last) {
+    __device__ __forceinline__ void step(const uint32_t *sdesc, unsigned char *lds, uint32_t lane_off,
+                                         uint32_t stride, int last) {
         const bool up = (cand == 0u);
         const int nd = up ? d - 1 : d + 1;
-        const uint32_t ndesc = desc[nd];
-        const uint32_t saved = stk[(up ? d - 1 : d) * stride];
+        const uint32_t ndesc = sdesc[nd];
+        const uint32_t saved = *reinterpret_cast<const S *>(lds + (lane_off + (uint32_t)(up ? d - 1 : d) * stride));
+        // up lanes write 0 into a slot nobody reads again
+        *reinterpret_cast<S *>(lds + (lane_off + (uint32_t)d * stride)) = (S)cand;
         const uint32_t stored = up ? saved : cand;
         const uint32_t b = stored & (0u - stored);
         toggle(up ? ndesc : cur, b);
-        if (!up) stk[d * stride] = (S)cand;
-        uint32_t nc = cands(ndesc);
-        if (nd == last) {               // last cell: count its candidates
-            cnt += (uint64_t)__builtin_popcount(nc);
-            nc = 0u;
-        }
-        cand = up ? (stored ^ b) : nc;
+        const uint32_t nc = cands(ndesc);
+        const bool leaf = (nd == last);
+        cnt += leaf ? (uint64_t)__builtin_popcount(nc) : 0ull;
+        cand = up ? (stored ^ b) : (leaf ? 0u : nc);
         cur = ndesc;
         d = nd;
     }
 
-    // Load a prefix (n*n bytes in registers-sized chunks from global memory)
-    // and check it against the pattern.  Returns false if it breaks a
-    // constraint (count 0); sets *mismatch if it does not fit the pattern.
-    __device__ __forceinline__ bool load(const uint8_t *sq, const uint32_t *patbits,
-                                         bool *mismatch) {
-        clear();
-        uint32_t bad = 0u, mis = 0u;
-        // the whole square is read as dwords; cells are unpacked at
-        // compile-time offsets
-        constexpr int NN = N * N;
-        constexpr int NW = (NN + 3) / 4;
-        uint32_t words[NW];
+    __device__ __forceinline__ void from_rec(const Rec<N, VS> &r, const uint32_t *sdesc, int last) {
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            uint32_t w = 0;
+        for (int k = 0; k < G::WR; ++k) R[k] = r.R[k];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int c = 4 * k + t;
-                if (c < NN) w |= (uint32_t)sq[c] << (8 * t);
-            }
-            words[k] = w;
+        for (int k = 0; k < G::WC; ++k) C[k] = r.C[k];
+        md = r.diag & 0xFFFFu;
+        ad = r.diag >> 16;
+        cnt = 0;
+        const uint32_t lvl = r.cl >> 16;
+        if (lvl == kNone) {
+            cand = 0u;
+            d = start = 0;
+            return;
         }
-#pragma unroll
-        for (int c = 0; c < NN; ++c) {
-            const int i = c / N, j = c % N;
-            const uint32_t v = (words[c >> 2] >> (8 * (c & 3))) & 0xFFu;
-            const bool inpat = (patbits[c >> 5] >> (c & 31)) & 1u;
-            const bool filled = v != 0xFFu;
-            mis |= (inpat != filled) || (filled && v >= (uint32_t)N);
-            if (!inpat || !filled || v >= (uint32_t)N) continue;
-            if constexpr (VS) {
-                if (2 * j > N - 1) continue;   // right half: checked via its mirror
-                const int mc = i * N + (N - 1 - j);
-                const uint32_t w = (words[mc >> 2] >> (8 * (mc & 3))) & 0xFFu;
-                bad |= (w != (uint32_t)(N - 1) - v) ? 1u : 0u;
-                const uint32_t b = 1u << v, rb = 1u << (N - 1 - v);
-                const int rw = i / Geo<N>::LPW, rs = (i % Geo<N>::LPW) * N;
-                const int cw = j / Geo<N>::LPW, cs = (j % Geo<N>::LPW) * N;
-                const uint32_t rbits = (b | rb) << rs, cbits = b << cs;
-                bad |= (R[rw] & rbits) | (C[cw] & cbits);
-                if (2 * j == N - 1) bad |= 1u;  // odd order: middle column impossible
-                R[rw] |= rbits;
-                C[cw] |= cbits;
-                if (i == j) {
-                    bad |= (md & b) | (ad & rb);
-                    md |= b;
-                    ad |= rb;
-                }
-                if (i + j == N - 1) {
-                    bad |= (ad & b) | (md & rb);
-                    ad |= b;
-                    md |= rb;
-                }
-            } else {
-                const uint32_t b = 1u << v;
-                const int rw = i / Geo<N>::LPW, rs = (i % Geo<N>::LPW) * N;
-                const int cw = j / Geo<N>::LPW, cs = (j % Geo<N>::LPW) * N;
-                const uint32_t rbits = b << rs, cbits = b << cs;
-                bad |= (R[rw] & rbits) | (C[cw] & cbits);
-                R[rw] |= rbits;
-                C[cw] |= cbits;
-                if (i == j) {
-                    bad |= md & b;
-                    md |= b;
-                }
-                if (i + j == N - 1) {
-                    bad |= ad & b;
-                    ad |= b;
-                }
-            }
-        }
-        *mismatch = mis != 0u;
-        return bad == 0u && mis == 0u;
-    }
-
-    // Start a task at level `lvl` (all levels below it already applied).
-    __device__ __forceinline__ void begin(const uint32_t *desc, int lvl, int nlev, uint32_t c) {
-        start = d = lvl;
-        cur = desc[lvl];
-        cand = c;
-        if (lvl == nlev - 1) {
-            cnt += (uint64_t)__builtin_popcount(cand);
+        cand = r.cl & 0xFFFFu;
+        d = start = (int)lvl;
+        cur = sdesc[lvl];
+        if ((int)lvl == last) {
+            cnt = (uint64_t)__builtin_popcount(cand);
             cand = 0u;
         }
     }
 };
 
-// stack element type: 8 bits suffice up to N = 8
+// stack element: 8 bits suffice up to N = 8
 template <int N>
 using StackT = typename std::conditional<(N <= 8), uint8_t, uint16_t>::type;
 
+// LDS layout of the search kernels: level descriptors, then the stacks, then
+// (persistent kernel) one mailbox of 64 task records per wave
+constexpr uint32_t kStackBase = sizeof(uint32_t) * kMaxLevels;
+
+__host__ __device__ inline uint32_t mailbox_offset(int nlev, int block, int elem) {
+    const uint32_t end = kStackBase + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
+    return (end + 15u) & ~15u;
+}
+
 // ---------------------------------------------------------------------------
-// plain kernel: one prefix per lane, run to completion
+// prep: prefix cells -> task record (one lane per prefix)
+// ---------------------------------------------------------------------------
+
+template <int N, bool VS>
+__global__ void __launch_bounds__(256) prep_kernel(const Plan plan, const uint8_t *__restrict__ prefixes,
+                                                   int64_t num, Rec<N, VS> *__restrict__ recs,
+                                                   uint64_t *__restrict__ counts, uint32_t *status) {
+    using G = Geo<N, VS>;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= num) return;
+    constexpr int NN = N * N;
+    constexpr int NW = (NN + 3) / 4;
+    const uint8_t *sq = prefixes + idx * NN;
+    uint32_t words[NW];
+    if constexpr (NN % 4 == 0) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(sq);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) words[k] = w[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (4 * k + t < NN) x |= (uint32_t)sq[4 * k + t] << (8 * t);
+            words[k] = x;
+        }
+    }
+    Lane<N, VS> L;
+#pragma unroll
+    for (int k = 0; k < G::WR; ++k) L.R[k] = 0;
+#pragma unroll
+    for (int k = 0; k < G::WC; ++k) L.C[k] = 0;
+    L.md = L.ad = 0u;
+    uint64_t bad = 0;
+    uint32_t mis = 0u;
+#pragma unroll
+    for (int c = 0; c < NN; ++c) {
+        const int i = c / N, j = c % N;
+        const uint32_t v = (words[c >> 2] >> (8 * (c & 3))) & 0xFFu;
+        const bool inpat = (plan.patbits[c >> 5] >> (c & 31)) & 1u;
+        const bool filled = v != 0xFFu;
+        mis |= ((inpat != filled) || (filled && v >= (uint32_t)N)) ? 1u : 0u;
+        if (!inpat || !filled || v >= (uint32_t)N) continue;
+        const uint32_t b = 1u << v;
+        const int rw = i / G::LPW, rs = (i % G::LPW) * N;
+        if constexpr (VS) {
+            if (2 * j > N - 1) continue;  // right half: taken care of through its mirror
+            const int mc = i * N + (N - 1 - j);
+            const uint32_t w = (words[mc >> 2] >> (8 * (mc & 3))) & 0xFFu;
+            bad |= (w != (uint32_t)(N - 1) - v) ? 1u : 0u;
+            // a cell on the middle column (odd N) is its own mirror: v = (N-1)/2
+            const bool self = (2 * j == N - 1);
+            if (self) bad |= (2 * v != (uint32_t)(N - 1)) ? 1u : 0u;
+            const uint32_t rb = self ? 0u : 1u << (N - 1 - v);
+            const int cw = j / G::LPW, cs = (j % G::LPW) * N;
+            const uint64_t rbits = (uint64_t)(b | rb) << rs, cbits = (uint64_t)b << cs;
+            bad |= (L.R[rw] & rbits) | (L.C[cw] & cbits);
+            L.R[rw] |= rbits;
+            L.C[cw] |= cbits;
+            if (i == j) {
+                bad |= (L.md & b) | (L.ad & rb);
+                L.md |= b;
+                L.ad |= rb;
+            }
+            if (i + j == N - 1) {
+                bad |= (L.ad & b) | (L.md & rb);
+                L.ad |= b;
+                L.md |= rb;
+            }
+        } else {
+            const int cw = j / G::LPW, cs = (j % G::LPW) * N;
+            const uint64_t rbits = (uint64_t)b << rs, cbits = (uint64_t)b << cs;
+            bad |= (L.R[rw] & rbits) | (L.C[cw] & cbits);
+            L.R[rw] |= rbits;
+            L.C[cw] |= cbits;
+            if (i == j) {
+                bad |= L.md & b;
+                L.md |= b;
+            }
+            if (i + j == N - 1) {
+                bad |= L.ad & b;
+                L.ad |= b;
+            }
+        }
+    }
+    if (mis && status) atomicOr(status, 1u);
+    Rec<N, VS> r;
+#pragma unroll
+    for (int k = 0; k < G::WR; ++k) r.R[k] = L.R[k];
+#pragma unroll
+    for (int k = 0; k < G::WC; ++k) r.C[k] = L.C[k];
+    r.diag = L.md | (L.ad << 16);
+    r.origin = (uint32_t)idx;
+    r.pad = 0;
+    const int nlev = plan.nlev;
+    uint64_t count = 0;
+    if (bad || mis) {
+        r.cl = kNone << 16;
+    } else if (nlev == 0) {
+        count = 1;  // a complete, consistent square
+        r.cl = kNone << 16;
+    } else {
+        const uint32_t c0 = L.cands(plan.desc[0]);
+        if (nlev == 1) {
+            count = (uint64_t)__builtin_popcount(c0);
+            r.cl = kNone << 16;
+        } else {
+            r.cl = c0;  // level 0
+        }
+    }
+    recs[idx] = r;
+    counts[idx] = count;
+}
+
+// ---------------------------------------------------------------------------
+// plain kernel: one task per lane, run to completion
 // ---------------------------------------------------------------------------
 
 template <int N, bool VS, bool STATS>
-__global__ void __launch_bounds__(1024) plain_kernel(const Plan plan, const uint8_t *__restrict__ prefixes,
+__global__ void __launch_bounds__(1024) plain_kernel(const Plan plan, const Rec<N, VS> *__restrict__ recs,
                                                      int64_t num, uint64_t *__restrict__ counts,
-                                                     uint32_t *status, uint64_t *steps) {
+                                                     uint64_t *steps) {
     using S = StackT<N>;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *sdesc = reinterpret_cast<uint32_t *>(smem);
-    S *sstk = reinterpret_cast<S *>(smem + sizeof(uint32_t) * kMaxLevels);
     const int nlev = plan.nlev;
     for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
     __syncthreads();
 
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= num) return;
+    const Rec<N, VS> r = recs[idx];
+    if ((r.cl >> 16) == kNone) return;  // result already written by the prep kernel
     Lane<N, VS> L;
-    bool mismatch = false;
-    const bool ok = L.load(prefixes + idx * (N * N), plan.patbits, &mismatch);
-    if (mismatch && status) atomicOr(status, 1u);
+    L.from_rec(r, sdesc, nlev - 1);
+    const uint32_t lane_off = kStackBase + threadIdx.x * (uint32_t)sizeof(S);
+    const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
     uint64_t nsteps = 0;
-    if (nlev == 0) {
-        L.cnt = ok ? 1u : 0u;
-    } else if (ok) {
-        L.begin(sdesc, 0, nlev, L.cands(sdesc[0]));
-        S *stk = sstk + threadIdx.x;
-        const int stride = blockDim.x;
-        while (!L.done()) {
-            L.step(sdesc, stk, stride, nlev - 1);
-            if (STATS) ++nsteps;
-        }
+    while (!L.done()) {
+        L.template step<S>(sdesc, smem, lane_off, stride, nlev - 1);
+        if (STATS) ++nsteps;
     }
     counts[idx] = L.cnt;
     if (STATS && steps) atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
 }
 
 // ---------------------------------------------------------------------------
-// persistent kernel: global queue of prefixes + donated subtrees
+// persistent kernel: global queue of tasks, lane-level refill, and donation
+// of untried siblings when the static queue is exhausted
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// broadcast a 64-bit value from a (wave-uniform) lane
 __device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
     return ((uint64_t)hi << 32) | lo;
 }
 
-// s_memrealtime ticks at 100 MHz
-constexpr uint64_t kStallTicks = 100000000ull * 20;  // 20 s without any queue progress
+// s_memrealtime ticks at 100 MHz: 20 s without any queue progress ends the kernel
+constexpr uint64_t kStallTicks = 100000000ull * 20;
+
+// Give away the untried siblings at level lvl of a lane's search: the record
+// holds the masks as they were on entering lvl (the values taken at levels
+// lvl..d-1 cleared again) and the candidates not yet tried there; the lane
+// keeps only the branch in progress.
+template <int N, bool VS, class SlotOf>
+__device__ __forceinline__ Rec<N, VS> donate(const Lane<N, VS> &L, int lvl, const uint32_t *sdesc, SlotOf slot_of,
+                                             uint32_t origin) {
+    Lane<N, VS> T = L;
+    for (int l = L.d - 1; l >= lvl; --l) {
+        const uint32_t sv = *slot_of(l);
+        T.toggle(sdesc[l], sv & (0u - sv));
+    }
+    const uint32_t sv = *slot_of(lvl);
+    const uint32_t b = sv & (0u - sv);
+    Rec<N, VS> r;
+#pragma unroll
+    for (int k = 0; k < Geo<N, VS>::WR; ++k) r.R[k] = T.R[k];
+#pragma unroll
+    for (int k = 0; k < Geo<N, VS>::WC; ++k) r.C[k] = T.C[k];
+    r.diag = T.md | (T.ad << 16);
+    r.cl = (sv ^ b) | ((uint32_t)lvl << 16);
+    r.origin = origin;
+    r.pad = 0;
+    *slot_of(lvl) = (decltype(*slot_of(lvl) + 0))b;
+    return r;
+}
+
+// s_waitcnt immediate for gfx9: vmcnt <= 1 (bits 3:0 and 15:14), no wait on
+// expcnt (bits 6:4 = 7) or lgkmcnt (bits 11:8 = 15)
+constexpr int kWaitVm1 = 0x0F71;
+constexpr int kWaitVm0 = 0x0F70;
 
 template <int N, bool VS, bool STATS>
-__global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const uint8_t *__restrict__ prefixes,
-                                                          int64_t num, uint64_t *__restrict__ counts,
-                                                          uint32_t *status, uint64_t *steps,
-                                                          Ctrl *ctrl, Item *items, int64_t item_cap,
-                                                          Tuning tune) {
+__global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const Rec<N, VS> *recs, int64_t num,
+                                                          uint64_t *counts, uint32_t *status, uint64_t *steps,
+                                                          Ctrl *ctrl, Rec<N, VS> *items, uint32_t *ready,
+                                                          int64_t item_cap, Tuning tune) {
     using S = StackT<N>;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *sdesc = reinterpret_cast<uint32_t *>(smem);
-    S *sstk = reinterpret_cast<S *>(smem + sizeof(uint32_t) * kMaxLevels);
     const int nlev = plan.nlev;
     for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    S *stk = sstk + threadIdx.x;
-    const int stride = blockDim.x;
+    const bool poller = (threadIdx.x >> 6) == 0;  // one wave per workgroup waits for donations
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t lane_off = kStackBase + threadIdx.x * (uint32_t)sizeof(S);
+    const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
+    auto slot_of = [&](int l) -> S * { return reinterpret_cast<S *>(smem + (lane_off + (uint32_t)l * stride)); };
     const int last = nlev - 1;
     const uint64_t cap = (uint64_t)item_cap;
+    // donation across the chip is on only with a positive steal_depth
+    const int lim = tune.steal_depth > 0 ? nlev - tune.steal_depth : 0;
+    const uint64_t total_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+
+    // this wave counts as busy from its start until it finds no work anywhere
+    if (lane == 0) atomicAdd((unsigned long long *)&ctrl->busy, 1ull);
+    bool marked = true;
 
     Lane<N, VS> L;
     L.cand = 0u;
     L.d = L.start = 0;
     L.cnt = 0;
-    bool has = false;          // lane holds a task (possibly finished)
-    uint32_t origin = 0;
-    bool static_left = true;   // wave-uniform: static prefixes may remain
+    bool has = false;           // lane holds a task (possibly finished)
+    uint64_t *out = &ctrl->sink;  // where this lane's task count goes (a sink until the first task)
+    uint64_t stored = 0;        // part of L.cnt already in *out
+    bool static_left = true;    // wave-uniform
+    uint64_t cb = 0, ce = 0;    // wave-private range of static tasks
     uint64_t nsteps = 0;
     uint64_t seen_sig = ~0ull, seen_at = 0;
+    uint32_t backoff = 1, tick = 0;
+    bool asked = false;         // this (idle poller) wave is counted in ctrl->hungry
+    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(smem + mailbox_offset(nlev, blockDim.x, sizeof(S))) +
+                       (threadIdx.x & ~63u);
 
     for (;;) {
-        // ---------------- retire finished tasks ----------------
-        if (has && L.done()) {
-            if (L.cnt) atomicAdd((unsigned long long *)&counts[origin], (unsigned long long)L.cnt);
-            atomicAdd((unsigned long long *)&ctrl->outstanding, ~0ull);  // -1
-            has = false;
-            L.cnt = 0;
+        // ---------------- search ----------------
+        for (int it = 0; it < tune.refill_every; ++it) {
+            if (has && !L.done()) {
+                L.template step<S>(sdesc, smem, lane_off, stride, last);
+                if (STATS) ++nsteps;
+            }
         }
-        // ---------------- refill from the static queue (one atomic per wave) ----------------
-        uint64_t want = __ballot(!has);
-        if (want && static_left) {
-            const uint32_t k = (uint32_t)__popcll(want);
-            const int leader = __ffsll((unsigned long long)want) - 1;
-            uint64_t base = 0;
-            if (lane == leader) base = atomicAdd((unsigned long long *)&ctrl->head, (unsigned long long)k);
-            base = bcast64(base, leader);
-            if (base + k >= (uint64_t)num) static_left = false;
-            if (!has) {
-                const uint64_t rank = (uint64_t)__popcll(want & ((1ull << lane) - 1ull));
-                const uint64_t id = base + rank;
-                if (id < (uint64_t)num) {
-                    bool mismatch = false;
-                    origin = (uint32_t)id;
+        const bool fin = has && L.done();
+        uint64_t want = __ballot(!has || fin);
+
+        if (static_left) {
+            // ------------- retire + refill from the static queue -------------
+            // While static tasks remain no lane gives work away, so each count
+            // has a single writer: the lane stores its running count (the last
+            // store is the final one) instead of adding atomically.  Tasks come
+            // from a wave-private range refilled with a guided chunk
+            // (remaining / (2 * waves)) by one atomic on ctrl->head.  Every
+            // lane issues the same memory operations (one record load, then
+            // one count store), so the wait below covers the loads only.
+            if (want && (__popcll(want) >= tune.refill_min || want == ~0ull)) {
+                const bool idle = !has || fin;
+                const uint64_t k = (uint64_t)__popcll(want);
+                const uint64_t rank = (uint64_t)__popcll(want & below);
+                const int leader = __ffsll((unsigned long long)want) - 1;
+                int64_t my_id = -1;
+                uint64_t given = 0;
+                while (given < k) {
+                    if (cb >= ce) {
+                        const uint64_t rem = (uint64_t)num > ce ? (uint64_t)num - ce : 0;
+                        uint64_t sz = rem / (2 * total_waves);
+                        sz = sz < 64 ? 64 : (sz > 65536 ? 65536 : sz);
+                        uint64_t base = 0;
+                        if (lane == leader)
+                            base = atomicAdd((unsigned long long *)&ctrl->head, (unsigned long long)sz);
+                        base = bcast64(base, leader);
+                        if (base >= (uint64_t)num) {
+                            static_left = false;
+                            break;
+                        }
+                        cb = base;
+                        ce = base + sz < (uint64_t)num ? base + sz : (uint64_t)num;
+                    }
+                    const uint64_t take = (k - given) < (ce - cb) ? (k - given) : (ce - cb);
+                    if (idle && rank >= given && rank < given + take) my_id = (int64_t)(cb + (rank - given));
+                    cb += take;
+                    given += take;
+                }
+                const Rec<N, VS> r = recs[my_id >= 0 ? my_id : 0];
+                asm volatile("" ::: "memory");  // keep the load ahead of the store
+                *out = L.cnt;
+                stored = L.cnt;
+                __builtin_amdgcn_s_waitcnt(kWaitVm1);
+                if (fin) has = false;
+                if (my_id >= 0) {
+                    L.from_rec(r, sdesc, last);
+                    out = &counts[r.origin];
+                    stored = 0;
                     has = true;
-                    const bool ok = L.load(prefixes + id * (N * N), plan.patbits, &mismatch);
-                    if (mismatch && status) atomicOr(status, 1u);
-                    L.cand = 0u;
-                    L.d = L.start = 0;
-                    if (nlev == 0)
-                        L.cnt = ok ? 1u : 0u;
-                    else if (ok)
-                        L.begin(sdesc, 0, nlev, L.cands(sdesc[0]));
                 }
             }
-            want = __ballot(!has);
+            continue;
         }
-        // ---------------- refill from donated subtrees ----------------
-        if (want && !static_left) {
+
+        // ================= tail: the static queue is exhausted =================
+        // Counts may now have several writers (donated subtrees): add the part
+        // not yet stored.
+        if (fin) {
+            if (L.cnt != stored) atomicAdd((unsigned long long *)out, (unsigned long long)(L.cnt - stored));
+            has = false;
+            L.cnt = 0;
+            stored = 0;
+        }
+        want = __ballot(!has);
+        // ---------------- share work inside the wave (LDS mailbox) ----------------
+        // busy lanes hand the untried siblings at their shallowest open level
+        // to idle lanes of the same wave, as task records
+        if (want && want != ~0ull) {
+            int lvl = -1;
+            if (has && !L.done()) {
+                const int top = L.d < last - 1 ? L.d : last - 1;
+                for (int l = L.start; l < top; ++l) {
+                    const uint32_t sv = *slot_of(l);
+                    if (sv & (sv - 1u)) {
+                        lvl = l;
+                        break;
+                    }
+                }
+            }
+            const uint64_t donors = __ballot(lvl >= 0);
+            const uint64_t nd = (uint64_t)__popcll(donors), ni = (uint64_t)__popcll(want);
+            const uint64_t m = nd < ni ? nd : ni;
+            if (m) {
+                const uint64_t drank = (uint64_t)__popcll(donors & below);
+                const uint64_t rrank = (uint64_t)__popcll(want & below);
+                if (lvl >= 0 && drank < m) {
+                    const Rec<N, VS> r = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts));
+                    mbox[drank] = r;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                if (!has && rrank < m) {
+                    const Rec<N, VS> r = mbox[rrank];
+                    L.from_rec(r, sdesc, last);
+                    out = &counts[r.origin];
+                    stored = 0;
+                    has = true;
+                }
+                __builtin_amdgcn_wave_barrier();
+                want = __ballot(!has);
+            }
+        }
+        // the queue state is read once every few passes (or when idle)
+        ++tick;
+        if (want != ~0ull && (tick & (uint32_t)(tune.tail_poll - 1)) != 0) continue;
+        uint64_t rsv = 0, hd = 0, busy = 0, hungry = 0;
+        if (lane == 0) {
+            rsv = ld_relaxed(&ctrl->dq_reserve);
+            hd = ld_relaxed(&ctrl->dq_head);
+            busy = ld_relaxed(&ctrl->busy);
+            hungry = ld_relaxed(&ctrl->hungry);
+        }
+        rsv = bcast64(rsv, 0);
+        hd = bcast64(hd, 0);
+        busy = bcast64(busy, 0);
+        hungry = bcast64(hungry, 0);
+        if (rsv > cap) rsv = cap;
+        // ---------------- take donated subtrees ----------------
+        if (want && rsv > hd) {
             const uint32_t k = (uint32_t)__popcll(want);
             const int leader = __ffsll((unsigned long long)want) - 1;
             uint64_t h0 = 0, got = 0;
             if (lane == leader) {
-                uint64_t h = ld_relaxed(&ctrl->dq_head);
-                for (int tries = 0; tries < 64; ++tries) {
+                uint64_t h = hd;
+                for (int tries = 0; tries < 16; ++tries) {
                     uint64_t r = ld_relaxed(&ctrl->dq_reserve);
                     if (r > cap) r = cap;
                     const uint64_t avail = r > h ? r - h : 0;
@@ -366,56 +570,64 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                         break;
                     }
                 }
+                if (got && !marked) atomicAdd((unsigned long long *)&ctrl->busy, 1ull);
+                if (got && asked) atomicAdd((unsigned long long *)&ctrl->hungry, ~0ull);  // -1
             }
             h0 = bcast64(h0, leader);
             got = bcast64(got, leader);
+            if (got) {
+                marked = true;
+                asked = false;
+                backoff = 1;
+            }
             if (!has) {
-                const uint64_t rank = (uint64_t)__popcll(want & ((1ull << lane) - 1ull));
+                const uint64_t rank = (uint64_t)__popcll(want & below);
                 if (rank < got) {
-                    Item *it = items + (h0 + rank);
-                    // the slot was reserved by a running lane that publishes it
-                    // right after writing it; the wait is bounded all the same
+                    const uint64_t slot = h0 + rank;
+                    // the slot's writer publishes it right after reserving it
                     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-                    bool ready = false;
+                    bool ok = false;
                     for (;;) {
-                        if (__hip_atomic_load(&it->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                            ready = true;
+                        if (__hip_atomic_load(&ready[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+                            ok = true;
                             break;
                         }
                         if (__builtin_amdgcn_s_memrealtime() - t0 > kStallTicks) break;
                         __builtin_amdgcn_s_sleep(1);
                     }
-                    if (!ready) {
-                        if (status) atomicOr(status, 2u);
-                        atomicAdd((unsigned long long *)&ctrl->outstanding, ~0ull);
-                    } else {
+                    if (ok) {
                         __threadfence();
-                        origin = it->origin;
-                        const int lvl = it->level;
-                        const uint32_t icand = it->cand;
-                        bool mismatch = false;
-                        L.load(prefixes + (uint64_t)origin * (N * N), plan.patbits, &mismatch);
-                        for (int l = 0; l < lvl; ++l) {
-                            const uint32_t v = ((uint32_t)it->path[l >> 1] >> (4 * (l & 1))) & 15u;
-                            const uint32_t b = 1u << v;
-                            L.toggle(sdesc[l], b);
-                            stk[l * stride] = (S)b;
-                        }
-                        __hip_atomic_store(&it->ready, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        L.cnt = 0;
-                        L.begin(sdesc, lvl, nlev, icand);
+                        const Rec<N, VS> r = items[slot];
+                        __hip_atomic_store(&ready[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        L.from_rec(r, sdesc, last);
+                        out = &counts[r.origin];
+                        stored = 0;
                         has = true;
+                    } else if (status) {
+                        atomicOr(status, 2u);
                     }
                 }
             }
             want = __ballot(!has);
         }
         // ---------------- termination ----------------
-        if (want == __ballot(true) && !static_left) {
-            // every lane of this wave is idle and nothing could be taken
-            const uint64_t out = ld_relaxed(&ctrl->outstanding);
-            if (out == 0) break;
-            const uint64_t sig = out ^ (ld_relaxed(&ctrl->dq_reserve) << 20) ^ (ld_relaxed(&ctrl->dq_head) << 40);
+        if (want == ~0ull) {
+            if (marked) {
+                __threadfence();
+                if (lane == 0) atomicAdd((unsigned long long *)&ctrl->busy, ~0ull);  // -1
+                marked = false;
+            }
+            // a wave that is not its workgroup's poller leaves as soon as it
+            // is idle: the busy waves and the pollers finish the tail
+            if (!poller || (busy == 0 && hd >= rsv)) {
+                if (asked && lane == 0) atomicAdd((unsigned long long *)&ctrl->hungry, ~0ull);
+                break;
+            }
+            if (!asked) {
+                if (lane == 0) atomicAdd((unsigned long long *)&ctrl->hungry, 1ull);
+                asked = true;
+            }
+            const uint64_t sig = busy ^ (rsv << 20) ^ (hd << 40);
             const uint64_t now = __builtin_amdgcn_s_memrealtime();
             if (sig != seen_sig) {
                 seen_sig = sig;
@@ -424,83 +636,71 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                 if (lane == 0 && status) atomicOr(status, 2u);
                 break;
             }
-            __builtin_amdgcn_s_sleep(8);
+            for (uint32_t t = 0; t < backoff; ++t) __builtin_amdgcn_s_sleep(64);
+            backoff = backoff < 32 ? backoff * 2 : 32;
             continue;
         }
-        // ---------------- donate untried siblings when the queue runs dry ----------------
-        if (!static_left && has && !L.done() && cap > 0) {
-            const uint64_t r = ld_relaxed(&ctrl->dq_reserve);
-            const uint64_t h = ld_relaxed(&ctrl->dq_head);
-            if (r < cap && r - h < (uint64_t)tune.low_water) {
-                // shallowest stacked level with untried candidates
-                int lvl = -1;
-                const int lim = nlev - tune.steal_depth;
-                for (int l = L.start; l < L.d && l < lim; ++l) {
-                    const uint32_t s = stk[l * stride];
-                    if (s & (s - 1u)) {
+        // ---------------- donate to idle waves elsewhere ----------------
+        // only full waves give work away across the chip, only large subtrees
+        // (levels above the cut-off), and only as many as idle pollers ask for
+        if (cap > 0 && lim > 0 && want == 0 && hungry > rsv - hd) {
+            int lvl = -1;
+            if (!L.done()) {
+                const int top = L.d < lim ? L.d : lim;
+                for (int l = L.start; l < top; ++l) {
+                    const uint32_t sv = *slot_of(l);
+                    if (sv & (sv - 1u)) {
                         lvl = l;
                         break;
                     }
                 }
-                if (lvl >= 0) {
-                    const uint64_t slot = atomicAdd((unsigned long long *)&ctrl->dq_reserve, 1ull);
-                    if (slot < cap) {
-                        atomicAdd((unsigned long long *)&ctrl->outstanding, 1ull);
-                        const uint32_t s = stk[lvl * stride];
-                        const uint32_t b = s & (0u - s);
-                        Item *it = items + slot;
-                        it->origin = origin;
-                        it->level = (uint16_t)lvl;
-                        it->cand = (uint16_t)(s ^ b);
-                        for (int l = 0; l < lvl; l += 2) {
-                            uint32_t v = (uint32_t)__builtin_ctz((uint32_t)stk[l * stride]);
-                            if (l + 1 < lvl) v |= (uint32_t)__builtin_ctz((uint32_t)stk[(l + 1) * stride]) << 4;
-                            it->path[l >> 1] = (uint8_t)v;
-                        }
-                        stk[lvl * stride] = (S)b;
-                        __threadfence();
-                        __hip_atomic_store(&it->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    }
+            }
+            const uint64_t donors = __ballot(lvl >= 0);
+            uint64_t quota = hungry - (rsv - hd);
+            quota = quota < (uint64_t)tune.donate_max ? quota : (uint64_t)tune.donate_max;
+            if (lvl >= 0 && (uint64_t)__popcll(donors & below) < quota) {
+                const uint64_t slot = atomicAdd((unsigned long long *)&ctrl->dq_reserve, 1ull);
+                if (slot < cap) {
+                    items[slot] = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts));
+                    __threadfence();
+                    __hip_atomic_store(&ready[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
-        // ---------------- search ----------------
-        for (int it = 0; it < tune.refill_every; ++it) {
-            if (has && !L.done()) {
-                L.step(sdesc, stk, stride, last);
-                if (STATS) ++nsteps;
-            }
-        }
+        // the tail is rare: let every memory access of this pass finish here so
+        // that the search loop never waits on one
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }
     if (STATS && steps) atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
 }
 
-__global__ void reset_ctrl(Ctrl *ctrl, uint64_t num, uint64_t *counts, int64_t ncounts, uint32_t *status) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) {
-        ctrl->head = 0;
-        ctrl->dq_reserve = 0;
-        ctrl->dq_head = 0;
-        ctrl->outstanding = num;
-    }
-    for (int64_t k = t; k < ncounts; k += (int64_t)gridDim.x * blockDim.x) counts[k] = 0;
-}
-
 // ready flags of the slots the previous launch on this queue reserved (all
-// consumed after a normal end; cleared anyway in case that launch stopped early)
-__global__ void clear_used_items(const Ctrl *ctrl, Item *items, int64_t cap) {
+// consumed after a normal end; cleared anyway in case that launch stopped
+// early)
+__global__ void reset_queue(const Ctrl *ctrl, uint32_t *ready, int64_t cap) {
     const uint64_t r = ctrl->dq_reserve;
     const int64_t used = (int64_t)(r < (uint64_t)cap ? r : (uint64_t)cap);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t k = t; k < used; k += (int64_t)gridDim.x * blockDim.x) items[k].ready = 0u;
+    for (int64_t k = t; k < used; k += (int64_t)gridDim.x * blockDim.x) ready[k] = 0u;
 }
 
-__global__ void clear_items(Item *items, int64_t n) {
+__global__ void init_ctrl(Ctrl *ctrl) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->head = 0;
+        ctrl->dq_reserve = 0;
+        ctrl->dq_head = 0;
+        ctrl->busy = 0;
+        ctrl->sink = 0;
+        ctrl->hungry = 0;
+    }
+}
+
+__global__ void zero_u64(uint64_t *p, int64_t n) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) items[k].ready = 0u;
+    for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = 0;
 }
 
-// integer VALU probe: 8 independent and/or/xor/add chains per lane
+// integer VALU probe: 8 independent dependency chains of 32-bit xor/add/shift per lane
 __global__ void __launch_bounds__(256) valu_probe(int iters, uint32_t *sink) {
     uint32_t a[8];
 #pragma unroll
@@ -510,7 +710,7 @@ __global__ void __launch_bounds__(256) valu_probe(int iters, uint32_t *sink) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             a[k] = (a[k] ^ m) + 0x9E3779B9u;
-            a[k] = (a[k] | (m << 3)) & 0xFFFF7FFFu;
+            a[k] = (a[k] << 1) + (a[k] >> 31);
         }
     }
     uint32_t r = 0;
@@ -525,29 +725,33 @@ __global__ void __launch_bounds__(256) valu_probe(int iters, uint32_t *sink) {
 
 template <int N, bool VS>
 static hipError_t launch_n(const LaunchArgs &a) {
+    using R = Rec<N, VS>;
+    (void)hipGetLastError();  // drop an error left by an unrelated earlier call
     const int block = a.block;
-    const size_t lds = lds_bytes(N, a.plan.nlev, block);
+    const size_t lds = lds_bytes(N, VS, a.plan.nlev, block, a.persistent);
+    R *recs = reinterpret_cast<R *>(a.records);
+    const unsigned pgrid = (unsigned)((a.num + 255) / 256);
+    hipLaunchKernelGGL((prep_kernel<N, VS>), dim3(pgrid), dim3(256), 0, a.stream, a.plan, a.prefixes, a.num, recs,
+                       a.counts, a.status);
+    if (a.plan.nlev <= 1) return hipGetLastError();  // prep wrote every count
     if (a.persistent) {
-        const int grid = a.grid;
-        hipLaunchKernelGGL(clear_used_items, dim3(256), dim3(256), 0, a.stream, a.ctrl, a.items, a.item_cap);
-        hipLaunchKernelGGL(reset_ctrl, dim3(1024), dim3(256), 0, a.stream, a.ctrl, (uint64_t)a.num, a.counts,
-                           a.num, a.status);
+        hipLaunchKernelGGL(reset_queue, dim3(256), dim3(256), 0, a.stream, a.ctrl, a.ready, a.item_cap);
+        hipLaunchKernelGGL(init_ctrl, dim3(1), dim3(64), 0, a.stream, a.ctrl);
+        R *items = reinterpret_cast<R *>(a.items);
         if (a.steps)
-            hipLaunchKernelGGL((persistent_kernel<N, VS, true>), dim3(grid), dim3(block), lds, a.stream, a.plan,
-                               a.prefixes, a.num, a.counts, a.status, a.steps, a.ctrl, a.items, a.item_cap,
-                               a.tune);
+            hipLaunchKernelGGL((persistent_kernel<N, VS, true>), dim3(a.grid), dim3(block), lds, a.stream, a.plan,
+                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune);
         else
-            hipLaunchKernelGGL((persistent_kernel<N, VS, false>), dim3(grid), dim3(block), lds, a.stream, a.plan,
-                               a.prefixes, a.num, a.counts, a.status, a.steps, a.ctrl, a.items, a.item_cap,
-                               a.tune);
+            hipLaunchKernelGGL((persistent_kernel<N, VS, false>), dim3(a.grid), dim3(block), lds, a.stream, a.plan,
+                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune);
     } else {
         const int64_t grid = (a.num + block - 1) / block;
         if (a.steps)
             hipLaunchKernelGGL((plain_kernel<N, VS, true>), dim3((unsigned)grid), dim3(block), lds, a.stream, a.plan,
-                               a.prefixes, a.num, a.counts, a.status, a.steps);
+                               recs, a.num, a.counts, a.steps);
         else
             hipLaunchKernelGGL((plain_kernel<N, VS, false>), dim3((unsigned)grid), dim3(block), lds, a.stream,
-                               a.plan, a.prefixes, a.num, a.counts, a.status, a.steps);
+                               a.plan, recs, a.num, a.counts, a.steps);
     }
     return hipGetLastError();
 }
@@ -579,26 +783,44 @@ hipError_t launch(const LaunchArgs &a) {
     }
 }
 
-uint32_t make_desc(int n, int i, int j) {
-    const int lpw = 32 / n;
-    uint32_t d = (uint32_t)((i % lpw) * n) | (uint32_t)(i / lpw) << 5 | (uint32_t)((j % lpw) * n) << 8 |
-                 (uint32_t)(j / lpw) << 13;
+size_t record_bytes(int n, bool vs) {
+    switch (n) {
+#define DLS_REC_CASE(K) \
+    case K: return vs ? sizeof(Rec<K, true>) : sizeof(Rec<K, false>);
+        DLS_REC_CASE(1) DLS_REC_CASE(2) DLS_REC_CASE(3) DLS_REC_CASE(4) DLS_REC_CASE(5) DLS_REC_CASE(6)
+        DLS_REC_CASE(7) DLS_REC_CASE(8) DLS_REC_CASE(9) DLS_REC_CASE(10) DLS_REC_CASE(11) DLS_REC_CASE(12)
+        DLS_REC_CASE(13) DLS_REC_CASE(14) DLS_REC_CASE(15) DLS_REC_CASE(16)
+#undef DLS_REC_CASE
+        default: return 0;
+    }
+}
+
+uint32_t make_desc(int n, bool vs, int i, int j) {
+    (void)vs;
+    const int lpw = 64 / n;
+    uint32_t d = (uint32_t)((i % lpw) * n) | (uint32_t)(i / lpw) << 6 | (uint32_t)((j % lpw) * n) << 8 |
+                 (uint32_t)(j / lpw) << 14;
     if (i == j) d |= 1u << 16;
     if (i + j == n - 1) d |= 1u << 17;
     return d;
 }
 
-size_t lds_bytes(int n, int nlev, int block) {
-    const size_t elem = n <= 8 ? 1 : 2;
-    return sizeof(uint32_t) * kMaxLevels + elem * (size_t)(nlev > 1 ? nlev : 1) * block;
+size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent) {
+    const int elem = n <= 8 ? 1 : 2;
+    if (!persistent) return kStackBase + (size_t)elem * (size_t)(nlev > 1 ? nlev : 1) * block;
+    return mailbox_offset(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
 }
 
-hipError_t clear_item_flags(Item *items, int64_t n, hipStream_t stream) {
-    hipLaunchKernelGGL(clear_items, dim3(1024), dim3(256), 0, stream, items, n);
+hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream) {
+    (void)hipGetLastError();
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL(zero_u64, dim3(grid), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 
 hipError_t launch_valu_probe(int blocks, int iters, uint32_t *sink, hipStream_t stream) {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(valu_probe, dim3(blocks), dim3(256), 0, stream, iters, sink);
     return hipGetLastError();
 }

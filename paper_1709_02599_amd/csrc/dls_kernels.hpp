@@ -11,38 +11,36 @@ constexpr int kMaxLevels = 256;
 // Per-launch search plan: one descriptor per level of the fill order and the
 // set of cells every prefix of the batch assigns.
 struct Plan {
-    uint32_t desc[kMaxLevels];  // rsh | rw<<5 | csh<<8 | cw<<13 | md<<16 | ad<<17
-    uint32_t patbits[8];        // bit c set: cell c is assigned in every prefix
-    int nlev;                   // number of levels (cells the kernel fills)
+    // level descriptor: rsh | rw<<6 | csh<<8 | cw<<14 | onMD<<16 | onAD<<17,
+    // rsh/csh = bit offset of the cell's row/column line inside 64-bit word rw/cw
+    uint32_t desc[kMaxLevels];
+    uint32_t patbits[8];  // bit c set: cell c is assigned in every prefix
+    int nlev;             // number of levels (cells the kernels fill)
 };
 
 // Work-queue control block of the persistent kernel (device memory).
 struct Ctrl {
-    uint64_t head;         // next static prefix
+    uint64_t head;         // next static task
     uint64_t dq_reserve;   // donated slots reserved by producers
     uint64_t dq_head;      // donated slots taken by consumers
-    uint64_t outstanding;  // tasks taken or queued but not finished
-    uint64_t pad[4];
+    uint64_t busy;         // waves that may still hold or create work
+    uint64_t sink;         // count target of lanes that have not had a task yet
+    uint64_t hungry;       // idle poller waves waiting for donated work
+    uint64_t pad[2];
 };
-
-// A donated subtree: the origin prefix, the values taken at levels
-// 0..level-1 (4 bits each) and the candidate set left at `level`.
-struct Item {
-    uint32_t origin;
-    uint16_t level;
-    uint16_t cand;
-    uint32_t ready;        // 1 once published; consumers reset it to 0
-    uint8_t path[52];
-};
-static_assert(sizeof(Item) == 64, "Item layout");
-constexpr int kItemMaxLevels = 104;
 
 struct Tuning {
     int refill_every;  // DFS steps between queue visits
     int steal_depth;   // donate only levels < nlev - steal_depth
-    int low_water;     // donate while fewer donated items than this are queued
-    int pad;
+    int refill_min;    // idle lanes that trigger a refill while static work remains
+    int donate_max;    // donations per wave per queue visit
+    int donate_low;    // donate while fewer donated tasks than this are queued
+    int tail_poll;     // tail: read the queue state every tail_poll passes (power of 2)
 };
+
+// Size in bytes of one task record (packed masks of a partial square plus
+// level, candidates and origin) for order n; see Rec<> in dls_kernels.hip.
+size_t record_bytes(int n, bool vs);
 
 struct LaunchArgs {
     int n;
@@ -54,19 +52,21 @@ struct LaunchArgs {
     uint64_t *counts;
     uint32_t *status;
     uint64_t *steps;
+    void *records;         // num task records, written by the prep kernel
     int block;
     int grid;
     Ctrl *ctrl;
-    Item *items;
+    void *items;           // donated task records
+    uint32_t *ready;       // per donated slot: 1 once published
     int64_t item_cap;
     Tuning tune;
     hipStream_t stream;
 };
 
-uint32_t make_desc(int n, int i, int j);
+uint32_t make_desc(int n, bool vs, int i, int j);
 hipError_t launch(const LaunchArgs &a);
-hipError_t clear_item_flags(Item *items, int64_t n, hipStream_t stream);
 hipError_t launch_valu_probe(int blocks, int iters, uint32_t *sink, hipStream_t stream);
-size_t lds_bytes(int n, int nlev, int block);
+hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream);
+size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent);
 
 }  // namespace dlsk

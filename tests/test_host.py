@@ -233,3 +233,10 @@ def test_random_prefixes_are_consistent():
                 for j in range(n):
                     if a[i, j] != 255:
                         assert a[i, n - 1 - j] == n - 1 - a[i, j]
+
+
+def test_single_hip_runtime_in_process():
+    # the binding must bind libdls.so to the HIP runtime torch already loaded
+    with open("/proc/self/maps") as f:
+        libs = {line.split()[-1] for line in f if "libamdhip64" in line}
+    assert len(libs) <= 1, libs
