@@ -28,6 +28,28 @@ ORDER8_FIXED = 7447587840            # paper Sec. 5.1
 INT_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
 COPY_BYTES = 256 << 20          # calibration copy for the HBM byte counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "order8_symbreak_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1709_02599_amd", "csrc", "dls_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        vals = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.strip() and not line.startswith("#"):
+                    k, v = line.split()
+                    vals[k] = v
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if vals.get("kernel_source_sha256") != sha:
+            return None
+        return int(vals["fetch_bytes"]) + int(vals["write_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
 # algorithmic integer ops of Alg. 4 per unit (the per-unit model of the roofline):
 # a cell entry costs 3 (OR of the masks, XOR with AllN, loop test), an
 # assignment 9 (isolate 2, mark 2, unmark 2, clear lowest 2, loop test 1).  One
@@ -224,7 +246,7 @@ def main():
                    "order": n, "prefixes": num, "leaves_per_step": leaves,
                    "weighted_total": weighted, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": None},
+                     "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": measured_traffic()},
         "cpu_baseline": cpu,
         "plain_kernel": {"value": leaves / (results["plain"]["ms_per_step"] * 1e-3),
                          "ms_per_step": results["plain"]["ms_per_step"],
