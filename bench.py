@@ -198,7 +198,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        from paper_1709_02599_amd import workloads
+        import dls_workloads as workloads
         threads = oracle.default_threads()
         _, reps, _ = oracle.hourglass_classes(n, threads=threads)
         hc = oracle.hourglass_cells(n)

@@ -69,6 +69,10 @@ def _load():
     lib.oracle_assignments.argtypes = [ctypes.c_int, ctypes.c_int, u8p,
                                        ctypes.POINTER(ctypes.c_int), ctypes.c_int, u8p,
                                        ctypes.c_int64]
+    lib.oracle_assignments_at.restype = ctypes.c_int64
+    lib.oracle_assignments_at.argtypes = [ctypes.c_int, ctypes.c_int, u8p,
+                                          ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, u8p]
     lib.oracle_hourglass_group.restype = ctypes.c_int
     lib.oracle_hourglass_group.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int8),
                                            ctypes.POINTER(ctypes.c_int8), ctypes.c_int]
@@ -400,3 +404,18 @@ def count_assignments(n: int, base, cells: Sequence[int], vs: bool = False) -> i
     if k < 0:
         raise ValueError("invalid oracle input")
     return int(k)
+
+
+def assignments_at(n: int, base, cells: Sequence[int], positions, vs: bool = False) -> np.ndarray:
+    """The assignments ``assignments(n, base, cells, vs)`` would list at the
+    given increasing positions, without storing the others."""
+    b = _square(n, base)
+    c = (ctypes.c_int * max(1, len(cells)))(*cells)
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int64))
+    out = np.zeros((len(pos), n * n), dtype=np.uint8)
+    r = _load().oracle_assignments_at(n, int(bool(vs)), _u8(b), c, len(cells),
+                                      pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      len(pos), _u8(out))
+    if r < 0:
+        raise ValueError("invalid oracle input")
+    return out

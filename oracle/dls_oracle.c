@@ -593,3 +593,65 @@ int64_t oracle_hourglass_classes(int n, int vs, uint8_t *reps, uint32_t *mult,
     free(hg);
     return result;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Workunits at chosen positions of the depth-first enumeration.            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    or_state st;
+    const int *cells;
+    int k;
+    const int64_t *pos;   /* increasing positions wanted */
+    int64_t npos, next;   /* next index into pos          */
+    int64_t seen;         /* assignments enumerated so far */
+    uint8_t *out;
+} or_select;
+
+static void or_select_rec(or_select *e, int t)
+{
+    or_state *s = &e->st;
+    int n = s->n;
+    if (e->next >= e->npos) return;            /* all found: stop early */
+    if (t == e->k) {
+        if (e->seen == e->pos[e->next]) {
+            uint8_t *dst = e->out + e->next * n * n;
+            for (int c = 0; c < n * n; c++) {
+                int v = s->ls[c / n][c % n];
+                dst[c] = (uint8_t)(v < 0 ? OR_EMPTY : v);
+            }
+            e->next++;
+        }
+        e->seen++;
+        return;
+    }
+    int c = e->cells[t], i = c / n, j = c % n;
+    for (int v = 0; v < n; v++) {
+        if (!or_allowed(s, i, j, v)) continue;
+        or_mark(s, i, j, v, 1);
+        or_select_rec(e, t + 1);
+        or_mark(s, i, j, v, 0);
+    }
+}
+
+/* The assignments that oracle_assignments(n, vs, base, cells, k) would list
+ * at the given increasing positions, written in order; returns the total
+ * number of assignments enumerated (all of them if the last position is
+ * beyond the end), or -1 on invalid input. */
+int64_t oracle_assignments_at(int n, int vs, const uint8_t *base, const int *cells, int k,
+                              const int64_t *pos, int64_t npos, uint8_t *out)
+{
+    if (!or_check_args(n, base) || k < 0 || k > n * n || npos < 0) return -1;
+    for (int64_t t = 1; t < npos; t++) if (pos[t] <= pos[t - 1]) return -1;
+    or_select *e = (or_select *)malloc(sizeof(or_select));
+    if (!e) return -1;
+    int64_t r = 0;
+    if (or_load(&e->st, n, vs, base)) {
+        e->cells = cells; e->k = k; e->pos = pos; e->npos = npos; e->next = 0;
+        e->seen = 0; e->out = out;
+        or_select_rec(e, 0);
+        r = e->seen;
+    }
+    free(e);
+    return r;
+}

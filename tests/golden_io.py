@@ -52,3 +52,29 @@ def fig2():
             continue
         cur.extend(EMPTY if t == "_" else int(t) for t in line.split())
     return (np.array(blocks["left"], dtype=np.uint8), np.array(blocks["right"], dtype=np.uint8))
+
+
+def vs10_sample():
+    """The seeded VS order-10 sample written by make_vs10_sample.py:
+    (total workunits, left cells, positions, prefixes [K, 100], counts)."""
+    n = 10
+    total, cells, pos, rows, counts = None, None, [], [], []
+    for line in _lines("vs10_sample.txt"):
+        t = line.split()
+        if t[0] == "total":
+            total = int(t[1])
+        elif t[0] == "cells":
+            cells = [int(x) for x in t[1:]]
+        else:
+            p, digits, c = int(t[0]), t[1], int(t[2])
+            sq = np.full(n * n, EMPTY, dtype=np.uint8)
+            sq[:n] = np.arange(n)
+            for cell, d in zip(cells, digits):
+                v = int(d, 16)
+                i, j = divmod(cell, n)
+                sq[cell] = v
+                sq[i * n + (n - 1 - j)] = n - 1 - v
+            pos.append(p)
+            rows.append(sq)
+            counts.append(c)
+    return total, cells, np.array(pos, dtype=np.int64), np.stack(rows), np.array(counts, dtype=np.uint64)

@@ -14,7 +14,7 @@ from tests.gpu_helpers import gpu_counts, weighted_total
 pytestmark = pytest.mark.gpu
 
 dls = pytest.importorskip("paper_1709_02599_amd")
-from paper_1709_02599_amd import workloads  # noqa: E402
+import dls_workloads as workloads  # noqa: E402
 
 E = 0xFF
 KERNELS = [False, True]          # persistent, plain
@@ -230,3 +230,21 @@ def test_empty_batch():
     dls.dls_count_async(6, 0, None, d, 0, d)      # nothing to do
     torch.cuda.synchronize()
     assert dls.dls_count(6, 0, np.zeros((0, 36), np.uint8)).shape == (0,)
+
+
+def test_vs_order10_sampled_prefixes():
+    # 4096 seeded positions of the VS order-10 split at depth 17 (Sec. 5.4):
+    # the library's sampled prefixes equal the oracle's, every count equals
+    # the oracle's, and the estimate total x mean matches the paper's count
+    total, cells, pos, opre, ocounts = golden_io.vs10_sample()
+    pre, ptotal = dls.dls_split_sample(10, dls.DLS_VSYM, 17, pos)
+    assert ptotal == total
+    assert np.array_equal(pre, opre)
+    c, st = gpu_counts(dls, 10, dls.DLS_VSYM, pre)
+    assert st == 0
+    assert np.array_equal(c, ocounts)
+    x = c.astype(np.float64)
+    est = total * x.mean()
+    se = total * x.std(ddof=1) / np.sqrt(len(x))
+    paper = golden_io.counts()[(10, "vs_fixed")]
+    assert abs(est - paper) < 3 * se, (est, paper, se)

@@ -12,7 +12,7 @@ import oracle
 from tests import golden_io
 
 dls = pytest.importorskip("paper_1709_02599_amd")
-from paper_1709_02599_amd import workloads  # noqa: E402
+import dls_workloads as workloads  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
