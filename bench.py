@@ -59,6 +59,25 @@ OPS_PER_DOWN_STEP = 12
 OPS_PER_TASK = 3
 
 
+def tuned_launch(dls, torch):
+    """Launch settings for the order-8 workload from the autotuner's cache,
+    or the library defaults when it has not been tuned on this GPU."""
+    try:
+        from paper_1709_02599_amd import autotune
+        b = autotune.best(8, 0, "order8-symbreak-row1")
+    except Exception:
+        b = None
+    if not b:
+        return {}
+    return {k: b[k] for k in ("block", "refill_every", "order_variant") if k in b}
+
+
+def launch_of(dls, settings, time_kernel=0):
+    return dls.DlsLaunch(block=settings.get("block", 0), blocks_per_cu=0, steal_depth=0,
+                         refill_every=settings.get("refill_every", 0),
+                         order_variant=settings.get("order_variant", 0), time_kernel=time_kernel)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,18 +136,21 @@ def main():
     num = len(pre)
     pattern = (pre[0] != 0xFF).astype(np.uint8)
     d_pre = torch.from_numpy(pre).to(dev)
-    d_mult = torch.from_numpy(mult.astype(np.int64)).to(dev)
+    d_mult = torch.from_numpy(mult.astype(np.int32)).to(dev)   # class powers < 2^31
     d_cnt = torch.zeros(num, dtype=torch.int64, device=dev)
     d_status = torch.zeros(1, dtype=torch.int32, device=dev)
     d_steps = torch.zeros(1, dtype=torch.int64, device=dev)
+    d_total = torch.zeros(1, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
+    tuned = tuned_launch(dls, torch)
 
-    def run(flags, launch=None):
+    def run(flags, launch):
         dls.dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_status, stream, launch)
-        return (d_cnt * d_mult).sum()
+        dls.dls_reduce_weighted(d_cnt, d_mult, num, d_total, stream)
 
     # deterministic work measure: DFS steps of the whole batch (instrumented run)
-    dls.dls_count_async_stats(n, 0, pattern, d_pre, num, d_cnt, d_status, stream, None, d_steps)
+    dls.dls_count_async_stats(n, 0, pattern, d_pre, num, d_cnt, d_status, stream,
+                              launch_of(dls, tuned), d_steps)
     torch.cuda.synchronize()
     total_steps = int(d_steps.item())
     leaves = int(d_cnt.sum().item())
@@ -140,9 +162,9 @@ def main():
         # a few launches of each kernel, plus a device-to-device copy of known
         # size whose counter readings calibrate FETCH_SIZE / WRITE_SIZE
         for _ in range(3):
-            run(0)
+            run(0, launch_of(dls, tuned))
         for _ in range(3):
-            run(dls.DLS_PLAIN)
+            run(dls.DLS_PLAIN, launch_of(dls, {}))
         src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -152,23 +174,63 @@ def main():
                           "copy_bytes": COPY_BYTES}))
         return
 
+    # ---------------- timed region: K eager steps per kernel ----------------
+    # Each step is the prep kernel, the search kernel and the device
+    # reduction of the weighted total; the library records a HIP event pair
+    # around every search kernel on this stream.
     results = {}
-    for name, flags in (("persistent", 0), ("plain", dls.DLS_PLAIN)):
+    for name, flags, settings in (("persistent", 0, tuned), ("plain", dls.DLS_PLAIN, {})):
         for _ in range(args.warmup):
-            run(flags)
+            run(flags, launch_of(dls, settings))
         torch.cuda.synchronize()
-        timer = Timer(torch, stream)
+        timed = launch_of(dls, settings, time_kernel=1)
+        torch.cuda.synchronize()
         t_start = time.perf_counter()
-        tot = None
         for _ in range(args.steps):
-            with timer:
-                tot = run(flags)
+            run(flags, timed)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
-        st = int(d_status.item())
-        ok = int(tot.item()) == ORDER8_FIXED and st == 0
-        results[name] = {"ms_per_step": 1e3 * wall / args.steps, "kernel_ms": timer.mean_ms(),
-                         "exact": ok}
+        kernel_ms, launches = dls.dls_kernel_time_ms(stream)
+        assert launches == args.steps, launches
+        ok = int(d_total.item()) == ORDER8_FIXED and int(d_status.item()) == 0
+        results[name] = {"ms_per_step": 1e3 * wall / args.steps, "kernel_ms": kernel_ms, "exact": ok}
+
+    # ---------------- the same step captured in a HIP graph ----------------
+    from paper_1709_02599_amd.graphs import CountStep
+    graph = {}
+    step = CountStep(n, 0, pattern, d_pre, num, d_cnt, d_status, d_mult, launch_of(dls, tuned)).capture()
+    for _ in range(args.warmup):
+        step.replay()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        tot = step.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    graph["order8"] = {"ms_per_step": 1e3 * wall / args.steps,
+                       "dls_per_s": leaves / (wall / args.steps),
+                       "exact": int(tot.item()) == ORDER8_FIXED and int(d_status.item()) == 0}
+    del step
+    # order 7, split at the diagonals: a small batch where launch cost matters
+    pre7, mult7 = dls.dls_split(7, 0, 11)
+    d7 = torch.from_numpy(pre7).to(dev)
+    c7 = torch.zeros(len(pre7), dtype=torch.int64, device=dev)
+    pat7 = (pre7[0] != 0xFF).astype(np.uint8)
+    step7 = CountStep(7, 0, pat7, d7, len(pre7), c7, d_status).capture()
+    reps7 = 50
+    totals7 = {}
+    for name, fn in (("eager", step7.eager), ("graph", step7.replay)):
+        fn()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(reps7):
+            tot = fn()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        totals7[name] = int(tot.item())
+        graph["order7_" + name] = {"us_per_step": 1e6 * wall / reps7, "prefixes": len(pre7),
+                                   "count": totals7[name], "exact": totals7[name] == totals7.get("eager")}
+    del step7, d7, c7
 
     # ---------------- sustained variant: the full count, no symmetry breaking ----------------
     sustained = None
@@ -244,7 +306,8 @@ def main():
         "config": {"workload": "order-8 DLS, first row fixed, canonical hourglass symmetry "
                                "breaking, split at hourglass + row 1",
                    "order": n, "prefixes": num, "leaves_per_step": leaves,
-                   "weighted_total": weighted, "parallelism": "single GPU"},
+                   "weighted_total": weighted, "parallelism": "single GPU",
+                   "launch": tuned or "library defaults"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": measured_traffic()},
         "cpu_baseline": cpu,
@@ -252,13 +315,14 @@ def main():
                          "ms_per_step": results["plain"]["ms_per_step"],
                          "kernel_ms": results["plain"]["kernel_ms"]},
         "persistent_kernel_ms": p["kernel_ms"],
+        "graph": graph,
         "speedup_persistent_vs_plain": results["plain"]["ms_per_step"] / p["ms_per_step"],
         "effective_counted_per_s": weighted / (p["ms_per_step"] * 1e-3),
         "dfs_steps_per_launch": total_steps,
         "alg_ops_per_launch": alg_ops,
         "split_seconds_host": split_s,
         "sustained_full_count": sustained,
-        "exact": all(r["exact"] for r in results.values()),
+        "exact": all(r["exact"] for r in results.values()) and all(g["exact"] for g in graph.values()),
     }
     print(json.dumps(line))
 

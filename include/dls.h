@@ -52,7 +52,11 @@ enum {
     DLS_ERANGE = -2,   /* output capacity too small (required size reported)  */
     DLS_ENOMEM = -3,   /* host or device allocation failed                    */
     DLS_EDEVICE = -4,  /* HIP runtime error, no device, or kernel fault flag  */
-    DLS_EPATTERN = -5  /* a prefix's assigned cells differ from the pattern   */
+    DLS_EPATTERN = -5, /* a prefix's assigned cells differ from the pattern   */
+    DLS_ECAPTURE = -6  /* the stream is under HIP graph capture and the call
+                          would allocate (first call on the stream, or a
+                          larger batch than any before) or asked for
+                          kernel timing                                     */
 };
 
 const char *dls_strerror(int err);
@@ -78,6 +82,15 @@ const char *dls_last_hip_error(void);
  */
 int dls_order(int n, uint32_t flags, const uint8_t *assigned, uint8_t *order_out,
               int *len_out);
+
+/* Variants of the fill order for tuning (counts never depend on the order):
+ * 0 = the Sec. 2.3 rule as in dls_order; 1 ties broken column-major; 2 row
+ * counts weigh double in V; 3 column counts weigh double; 4 no forced-cell
+ * rule; 5 ties broken towards the last cell; 6 diagonal counts weigh double;
+ * 7 diagonals ignored in V.  Arguments as dls_order; DLS_EINVAL for an
+ * unknown variant. */
+int dls_order_variant(int n, uint32_t flags, const uint8_t *assigned, int variant,
+                      uint8_t *order_out, int *len_out);
 
 /*
  * Split into independent workunits (Sec. 5.2).  Starts from row 0 = 0..n-1
@@ -142,7 +155,19 @@ typedef struct {
                            0 = library default (on for batches too small to
                            fill the GPU), negative = off                       */
     int refill_every;   /* persistent kernel: DFS steps between refills       */
+    int order_variant;  /* fill-order variant (see dls_order_variant); 0 =
+                           the rule of Sec. 2.3.  Counts never depend on it. */
+    int time_kernel;    /* nonzero: record a HIP event pair around the
+                           search kernel on the launch stream (not under
+                           graph capture); read with dls_kernel_time_ms  */
 } dls_launch;
+
+/* Mean duration in milliseconds of the search kernels launched with
+ * time_kernel on `stream` since the previous call (at most 65536 launches),
+ * and their number in *launches_out (may be NULL).  Resets the tally.  The
+ * caller must have synchronised the stream.  DLS_EINVAL if no timed launch
+ * happened on it. */
+int dls_kernel_time_ms(void *stream, float *ms_out, int64_t *launches_out);
 
 /*
  * Exact counts on the GPU, device buffers, asynchronous on `stream`
@@ -171,6 +196,13 @@ int dls_count_async_stats(int n, uint32_t flags, const uint8_t *pattern,
                           const uint8_t *d_prefixes, int64_t num, uint64_t *d_counts,
                           uint32_t *d_status, void *stream, const dls_launch *launch,
                           uint64_t *d_steps);
+
+/* Device-side weighted total, the Corollary 1 sum:  *d_out = sum over k of
+ * d_mult[k] * d_counts[k] (d_mult NULL: all 1), uint64 arithmetic, on
+ * `stream`.  Launches only kernels (no memset), so it can be captured in a
+ * HIP graph with the counting launch. */
+int dls_reduce_weighted(const uint64_t *d_counts, const uint32_t *d_mult, int64_t num,
+                        uint64_t *d_out, void *stream);
 
 /* Integer-VALU throughput probe: `iters` rounds of independent 32-bit
  * and/or/xor/add chains on every lane of `blocks` x 256 threads; d_sink gets

@@ -20,12 +20,14 @@ __all__ = [
     "dls_version", "dls_strerror", "dls_last_hip_error", "dls_order", "dls_split", "dls_split_from",
     "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async",
     "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
+    "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms",
 ]
 
 DLS_VSYM = 1 << 0
 DLS_SYMBREAK = 1 << 1
 DLS_PLAIN = 1 << 2
 DLS_EMPTY = 0xFF
+DLS_ECAPTURE = -6
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdls.so")
 
@@ -39,7 +41,8 @@ class DLSError(RuntimeError):
 
 class DlsLaunch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
-                ("steal_depth", ctypes.c_int), ("refill_every", ctypes.c_int)]
+                ("steal_depth", ctypes.c_int), ("refill_every", ctypes.c_int),
+                ("order_variant", ctypes.c_int), ("time_kernel", ctypes.c_int)]
 
 
 def _load() -> ctypes.CDLL:
@@ -84,6 +87,11 @@ def _load() -> ctypes.CDLL:
                                                  ctypes.c_int64, vp, vp, vp,
                                                  ctypes.POINTER(DlsLaunch), vp]),
         "dls_valu_probe": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, vp]),
+        "dls_order_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int, u8p,
+                                             ctypes.POINTER(ctypes.c_int)]),
+        "dls_reduce_weighted": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
+        "dls_kernel_time_ms": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float),
+                                              ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -255,3 +263,27 @@ def dls_count_async_stats(n: int, flags: int, pattern, d_prefixes, num: int, d_c
 
 def dls_valu_probe(blocks: int, iters: int, d_sink, stream=None) -> None:
     _check(_lib.dls_valu_probe(blocks, iters, _ptr(d_sink), _stream(stream)), "dls_valu_probe")
+
+
+def dls_order_variant(n: int, flags: int, assigned, variant: int) -> list:
+    a = _square(n, assigned)
+    out = np.zeros(max(1, n * n), dtype=np.uint8)
+    ln = ctypes.c_int(0)
+    _check(_lib.dls_order_variant(n, flags, _u8(a), variant, _u8(out), ctypes.byref(ln)),
+           "dls_order_variant")
+    return [int(x) for x in out[:ln.value]]
+
+
+def dls_reduce_weighted(d_counts, d_mult, num: int, d_out, stream=None) -> None:
+    _check(_lib.dls_reduce_weighted(_ptr(d_counts), _ptr(d_mult), num, _ptr(d_out),
+                                    _stream(stream)), "dls_reduce_weighted")
+
+
+def dls_kernel_time_ms(stream=None):
+    """(mean ms, launches) of the search kernels timed on `stream` since the
+    previous call; the stream must have been synchronised."""
+    ms = ctypes.c_float(0.0)
+    k = ctypes.c_int64(0)
+    _check(_lib.dls_kernel_time_ms(_stream(stream), ctypes.byref(ms), ctypes.byref(k)),
+           "dls_kernel_time_ms")
+    return float(ms.value), int(k.value)

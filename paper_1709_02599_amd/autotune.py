@@ -1,0 +1,187 @@
+"""Autotuner for the persistent kernel.
+
+For one workload (a batch of prefixes of order N with flags) it times the
+counting launch on the GPU under every combination of
+
+* fill-order variant (`dls_order_variant`: the Sec. 2.3 rule and variants of
+  its weights and tie-breaks; the order changes the work, never the count),
+* workgroup size, and
+* refill cadence (DFS steps between queue visits),
+
+checks that every candidate returns the same counts (tuning cannot change a
+result), and keeps the fastest.  `tune_depth` does the same over split
+depths for a split workload (the split is host work; only the GPU launch is
+timed).  Results go to a JSON cache keyed by GPU architecture, order, flags
+and a workload name, read back by `best()`.
+
+    python -m paper_1709_02599_amd.autotune        # tunes the order-8 workload
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+from typing import Dict, Iterable, List, Optional
+
+import numpy as np
+
+from . import (DLS_PLAIN, DLS_SYMBREAK, DlsLaunch, dls_count_async_ex, dls_kernel_time_ms, dls_split)
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+VARIANTS = tuple(range(8))
+BLOCKS = (128, 256, 512)
+REFILLS = (16, 32, 64)
+
+
+def _arch(torch) -> str:
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def _load() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(cache: dict) -> None:
+    tmp = CACHE + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def key(arch: str, n: int, flags: int, workload: str) -> str:
+    return f"{arch}:{n}:{flags}:{workload}"
+
+
+def best(n: int, flags: int, workload: str, arch: Optional[str] = None) -> Optional[dict]:
+    """Tuned launch settings for a workload, or None if never tuned."""
+    cache = _load()
+    if arch is None:
+        import torch
+        arch = _arch(torch)
+    entry = cache.get(key(arch, n, flags, workload))
+    return entry["best"] if entry else None
+
+
+def time_launch(n: int, flags: int, pattern, d_pre, num: int, d_cnt, d_st, stream, launch: DlsLaunch,
+                reps: int = 3):
+    """Mean duration (ms) of the search kernel over `reps` launches, measured
+    by the library's event pairs on the launch stream, plus a digest of the
+    counts of the last launch and the device status."""
+    import torch
+    dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, launch)   # warm-up
+    timed = DlsLaunch(launch.block, launch.blocks_per_cu, launch.steal_depth, launch.refill_every,
+                      launch.order_variant, 1)
+    for _ in range(reps):
+        dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, timed)
+    torch.cuda.synchronize()
+    ms, k = dls_kernel_time_ms(stream)
+    assert k == reps
+    c = d_cnt[:num]
+    digest = (int(c.sum().item()), int((c * torch.arange(1, num + 1, device=c.device)).sum().item()))
+    return ms, digest, int(d_st.item())
+
+
+def tune(n: int, flags: int, prefixes: np.ndarray, workload: str,
+         variants: Iterable[int] = VARIANTS, blocks: Iterable[int] = BLOCKS,
+         refills: Iterable[int] = REFILLS, reps: int = 3, save: bool = True) -> dict:
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    pre = np.ascontiguousarray(prefixes, dtype=np.uint8)
+    num = len(pre)
+    pattern = (pre[0] != 0xFF).astype(np.uint8)
+    d_pre = torch.from_numpy(pre).to(dev)
+    d_cnt = torch.zeros(num, dtype=torch.int64, device=dev)
+    d_st = torch.zeros(1, dtype=torch.int32, device=dev)
+    table: List[dict] = []
+    ref = None
+    for v, blk, rf in itertools.product(variants, blocks, refills):
+        launch = DlsLaunch(block=blk, blocks_per_cu=0, steal_depth=0, refill_every=rf, order_variant=v)
+        ms, digest, st = time_launch(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, launch, reps)
+        if st:
+            raise RuntimeError(f"device status {st} for variant {v}, block {blk}, refill {rf}")
+        if ref is None:
+            ref = digest
+        elif digest != ref:
+            raise RuntimeError(f"counts differ for variant {v}, block {blk}, refill {rf}")
+        table.append({"order_variant": v, "block": blk, "refill_every": rf, "ms": ms})
+    # the plain kernel under the paper's order, for reference
+    plain_ms, digest, _ = time_launch(n, flags | DLS_PLAIN, pattern, d_pre, num, d_cnt, d_st, stream,
+                                      DlsLaunch(block=256), reps)
+    if digest != ref:
+        raise RuntimeError("plain kernel counts differ")
+    table.sort(key=lambda r: r["ms"])
+    default = [r for r in table if r["order_variant"] == 0 and r["block"] == 256 and r["refill_every"] == 32]
+    result = {"best": table[0], "default": default[0] if default else None, "plain_ms": plain_ms,
+              "candidates": len(table), "table": table[:12], "prefixes": num,
+              "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    if save:
+        cache = _load()
+        cache[key(_arch(torch), n, flags, workload)] = result
+        _save(cache)
+    return result
+
+
+def tune_depth(n: int, flags: int, depths: Iterable[int], workload: str, launch: Optional[dict] = None,
+               reps: int = 3, save: bool = True) -> dict:
+    """Time the counting launch for the split at each depth (same launch
+    settings); the weighted totals must agree."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    total_ref = None
+    for depth in depths:
+        t0 = time.perf_counter()
+        pre, mult = dls_split(n, flags, depth)
+        split_s = time.perf_counter() - t0
+        num = len(pre)
+        pattern = (pre[0] != 0xFF).astype(np.uint8)
+        d_pre = torch.from_numpy(pre).to(dev)
+        d_cnt = torch.zeros(num, dtype=torch.int64, device=dev)
+        d_st = torch.zeros(1, dtype=torch.int32, device=dev)
+        lc = DlsLaunch(**(launch or {}))
+        kflags = flags & ~DLS_SYMBREAK & 1
+        ms, _, st = time_launch(n, kflags, pattern, d_pre, num, d_cnt, d_st, stream, lc, reps)
+        tot = int((d_cnt * torch.from_numpy(mult.astype(np.int64)).to(dev)).sum().item())
+        if total_ref is None:
+            total_ref = tot
+        elif tot != total_ref or st:
+            raise RuntimeError(f"weighted total differs at depth {depth}")
+        rows.append({"depth": depth, "prefixes": num, "ms": ms, "split_s": split_s})
+    rows.sort(key=lambda r: r["ms"])
+    result = {"best": rows[0], "table": rows, "weighted_total": total_ref}
+    if save:
+        cache = _load()
+        cache[key(_arch(torch), n, flags, workload + ":depth")] = result
+        _save(cache)
+    return result
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args(argv)
+    pre, mult = dls_split(8, DLS_SYMBREAK, 26)
+    r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps)
+    print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
+                      "plain_ms": r["plain_ms"]}), flush=True)
+    d = tune_depth(8, DLS_SYMBREAK, (20, 22, 24, 26, 27, 28), "order8-symbreak",
+                   launch={k: r["best"][k] for k in ("block", "refill_every", "order_variant")},
+                   reps=args.reps)
+    print(json.dumps({"workload": "order8-symbreak", "depths": d["table"]}), flush=True)
+    spre, _ = dls_split(8, 0, 14)
+    s = tune(8, 0, spre, "order8-diag14", variants=(0, 1, 2, 3, 6), blocks=(256,), refills=(32,),
+             reps=1)
+    print(json.dumps({"workload": "order8-diag14", "best": s["best"], "default": s["default"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

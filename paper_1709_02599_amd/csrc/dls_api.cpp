@@ -84,7 +84,17 @@ struct QueueSlot {
     int64_t cap = 0;
     void *records = nullptr;    // task records of the batch in flight on this stream
     size_t records_bytes = 0;
+    // search-kernel timing: one event pair per timed launch since the last query
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t ev_used = 0;
 };
+
+constexpr size_t kMaxTimed = 1 << 16;
+
+bool capturing(void *stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
 
 struct DeviceState {
     bool init = false;
@@ -129,6 +139,8 @@ int device_state(DeviceState **out, int *dev_out) {
 int queue_slot(DeviceState *ds, void *stream, size_t records_bytes, QueueSlot **out) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     auto it = ds->slots.find(stream);
+    const bool cap = capturing(stream);
+    if (cap && (it == ds->slots.end() || it->second.records_bytes < records_bytes)) return DLS_ECAPTURE;
     if (it == ds->slots.end()) {
         QueueSlot s;
         if (hipMalloc((void **)&s.ctrl, sizeof(dlsk::Ctrl)) != hipSuccess) return DLS_ENOMEM;
@@ -159,7 +171,7 @@ int queue_slot(DeviceState *ds, void *stream, size_t records_bytes, QueueSlot **
     return DLS_OK;
 }
 
-int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan) {
+int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan, int variant = 0) {
     std::vector<uint8_t> pat((size_t)n * n, 0);
     if (pattern) {
         for (int c = 0; c < n * n; ++c) pat[c] = pattern[c] ? 1 : 0;
@@ -170,7 +182,8 @@ int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan) {
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j)
                 if (pat[i * n + j] != pat[i * n + (n - 1 - j)]) return DLS_EINVAL;
-    std::vector<int> order = dls::fill_order(n, vs, pat.data(), {});
+    if (variant < 0 || variant >= dls::kOrderVariants) return DLS_EINVAL;
+    std::vector<int> order = dls::fill_order(n, vs, pat.data(), {}, variant);
     if ((int)order.size() > dlsk::kMaxLevels) return DLS_EINVAL;
     std::memset(&plan, 0, sizeof(plan));
     plan.nlev = (int)order.size();
@@ -199,7 +212,7 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     }
     dlsk::LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
-    rc = build_plan(n, vs, pattern, a.plan);
+    rc = build_plan(n, vs, pattern, a.plan, launch ? launch->order_variant : 0);
     if (rc) return rc;
     a.n = n;
     a.vs = vs;
@@ -219,6 +232,21 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     rc = queue_slot(ds, stream, dlsk::record_bytes(n, vs) * (size_t)num, &qs);
     if (rc) return rc;
     a.records = qs->records;
+    if (launch && launch->time_kernel) {
+        if (capturing(stream)) return DLS_ECAPTURE;
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        if (qs->ev_used == qs->ev.size()) {
+            if (qs->ev.size() >= kMaxTimed) return DLS_ERANGE;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            hipError_t ec = hipEventCreate(&e0);
+            if (ec == hipSuccess) ec = hipEventCreate(&e1);
+            if (ec != hipSuccess) return hip_fail(ec, DLS_EDEVICE);
+            qs->ev.emplace_back(e0, e1);
+        }
+        a.ev_start = qs->ev[qs->ev_used].first;
+        a.ev_stop = qs->ev[qs->ev_used].second;
+        ++qs->ev_used;
+    }
     if (a.persistent) {
         a.ctrl = qs->ctrl;
         a.items = qs->items;
@@ -263,6 +291,9 @@ const char *dls_strerror(int err) {
         case DLS_ENOMEM: return "out of memory";
         case DLS_EDEVICE: return "HIP device error";
         case DLS_EPATTERN: return "prefix does not match the pattern";
+        case DLS_ECAPTURE: return "stream is being captured: device memory would have to be allocated "
+                                  "(make one uncaptured call with at least as many prefixes on this "
+                                  "stream first) or kernel timing was requested";
         default: return "unknown error";
     }
 }
@@ -451,6 +482,53 @@ int dls_count(int n, uint32_t flags, const uint8_t *prefixes, int64_t num, uint6
         return DLS_ENOMEM;
     }
     return DLS_OK;
+}
+
+int dls_kernel_time_ms(void *stream, float *ms_out, int64_t *launches_out) {
+    if (!ms_out) return DLS_EINVAL;
+    DeviceState *ds = nullptr;
+    int dev = 0;
+    int rc = device_state(&ds, &dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = ds->slots.find(stream);
+    if (it == ds->slots.end() || it->second.ev_used == 0) return DLS_EINVAL;
+    QueueSlot &q = it->second;
+    double sum = 0.0;
+    for (size_t k = 0; k < q.ev_used; ++k) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, q.ev[k].first, q.ev[k].second);
+        if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+        sum += ms;
+    }
+    *ms_out = (float)(sum / (double)q.ev_used);
+    if (launches_out) *launches_out = (int64_t)q.ev_used;
+    q.ev_used = 0;
+    return DLS_OK;
+}
+
+int dls_order_variant(int n, uint32_t flags, const uint8_t *assigned, int variant, uint8_t *order_out,
+                      int *len_out) {
+    if (!valid_n(n) || !assigned || !order_out || !len_out) return DLS_EINVAL;
+    if (flags & ~(uint32_t)(DLS_VSYM | DLS_SYMBREAK)) return DLS_EINVAL;
+    if (variant < 0 || variant >= dls::kOrderVariants) return DLS_EINVAL;
+    try {
+        std::vector<int> first;
+        if (flags & DLS_SYMBREAK) first = dls::hourglass_cells(n);
+        std::vector<int> o = dls::fill_order(n, flags & DLS_VSYM, assigned, first, variant);
+        for (size_t k = 0; k < o.size(); ++k) order_out[k] = (uint8_t)o[k];
+        *len_out = (int)o.size();
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int dls_reduce_weighted(const uint64_t *d_counts, const uint32_t *d_mult, int64_t num, uint64_t *d_out,
+                        void *stream) {
+    if (num < 0 || !d_out || (num > 0 && !d_counts)) return DLS_EINVAL;
+    hipError_t e = dlsk::launch_reduce_weighted(d_counts, d_mult, num, d_out, (hipStream_t)stream);
+    return e == hipSuccess ? DLS_OK : hip_fail(e, DLS_EDEVICE);
 }
 
 int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream) {

@@ -21,7 +21,11 @@ int host_threads() {
 // fill order (Sec. 2.3)
 // ---------------------------------------------------------------------------
 
-std::vector<int> fill_order(int n, bool vs, const uint8_t *assigned, const std::vector<int> &first) {
+std::vector<int> fill_order(int n, bool vs, const uint8_t *assigned, const std::vector<int> &first,
+                            int variant) {
+    const int wr = variant == 2 ? 2 : 1, wc = variant == 3 ? 2 : 1;
+    const int wd = variant == 6 ? 2 : (variant == 7 ? 0 : 1);
+    const bool forced_rule = variant != 4;
     const int nn = n * n;
     std::vector<uint8_t> a(nn, 0), pri(nn, 0);
     for (int c = 0; c < nn; ++c) a[c] = assigned[c] ? 1 : 0;
@@ -60,7 +64,7 @@ std::vector<int> fill_order(int n, bool vs, const uint8_t *assigned, const std::
         int pick = -1;
         auto consider_forced = [&](int c) {
             c = rep(c);
-            if (allowed[c] && (pick < 0 || c < pick)) pick = c;
+            if (forced_rule && allowed[c] && (pick < 0 || c < pick)) pick = c;
         };
         for (int i = 0; i < n; ++i)
             if (r[i] == n - 1)
@@ -79,10 +83,12 @@ std::vector<int> fill_order(int n, bool vs, const uint8_t *assigned, const std::
 
         if (pick < 0) {  // most constrained cell, first in row-major order on ties
             int best = -1;
-            for (int c = 0; c < nn; ++c) {
+            for (int t = 0; t < nn; ++t) {
+                // scan order: row-major (paper), column-major, or reversed
+                const int c = variant == 1 ? (t % n) * n + t / n : (variant == 5 ? nn - 1 - t : t);
                 if (!allowed[c]) continue;
                 int i = c / n, j = c % n;
-                int v = r[i] + col[j] + (i == j ? md : 0) + (i + j == n - 1 ? ad : 0);
+                int v = wr * r[i] + wc * col[j] + wd * ((i == j ? md : 0) + (i + j == n - 1 ? ad : 0));
                 if (v > best) {
                     best = v;
                     pick = c;

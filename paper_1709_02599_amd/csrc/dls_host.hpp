@@ -15,9 +15,14 @@ constexpr uint8_t kEmpty = 0xFF;
 // Fill order of the empty cells.  `assigned` has n*n entries (nonzero =
 // assigned); `first` (may be empty) lists cells that must come before all
 // others.  With vs, only left-half cells are listed and each pick also
-// assigns its mirror (i, n-1-j).
+// assigns its mirror (i, n-1-j).  `variant` 0 is the rule of Sec. 2.3; the
+// others change weights or tie-breaks for the autotuner (the count never
+// depends on the order): 1 column-major ties, 2 rows weigh double, 3 columns
+// weigh double, 4 no forced-cell rule, 5 last cell on ties, 6 diagonals
+// weigh double, 7 diagonals ignored.
+constexpr int kOrderVariants = 8;
 std::vector<int> fill_order(int n, bool vs, const uint8_t *assigned,
-                            const std::vector<int> &first);
+                            const std::vector<int> &first, int variant = 0);
 
 // Hourglass cells (Sec. 4.2): rows 0 and n-1 and both diagonals, row-major.
 std::vector<int> hourglass_cells(int n);

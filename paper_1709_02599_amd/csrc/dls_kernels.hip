@@ -700,6 +700,29 @@ __global__ void zero_u64(uint64_t *p, int64_t n) {
     for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = 0;
 }
 
+// out = sum_k mult[k] * counts[k] (mult == nullptr: all 1).  A first kernel
+// zeroes out; each workgroup of the second reduces its share in LDS and adds
+// it with one atomic.  Only kernels: the pair can be captured in a graph.
+__global__ void zero_one(uint64_t *out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = 0;
+}
+
+__global__ void __launch_bounds__(256) reduce_weighted(const uint64_t *__restrict__ counts,
+                                                       const uint32_t *__restrict__ mult, int64_t num,
+                                                       uint64_t *out) {
+    __shared__ uint64_t part[256];
+    uint64_t acc = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < num; k += (int64_t)gridDim.x * blockDim.x)
+        acc += counts[k] * (mult ? (uint64_t)mult[k] : 1ull);
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && part[0]) atomicAdd((unsigned long long *)out, (unsigned long long)part[0]);
+}
+
 // integer VALU probe: 8 independent dependency chains of 32-bit xor/add/shift per lane
 __global__ void __launch_bounds__(256) valu_probe(int iters, uint32_t *sink) {
     uint32_t a[8];
@@ -737,6 +760,9 @@ static hipError_t launch_n(const LaunchArgs &a) {
     if (a.persistent) {
         hipLaunchKernelGGL(reset_queue, dim3(256), dim3(256), 0, a.stream, a.ctrl, a.ready, a.item_cap);
         hipLaunchKernelGGL(init_ctrl, dim3(1), dim3(64), 0, a.stream, a.ctrl);
+    }
+    if (a.ev_start) (void)hipEventRecord(a.ev_start, a.stream);
+    if (a.persistent) {
         R *items = reinterpret_cast<R *>(a.items);
         if (a.steps)
             hipLaunchKernelGGL((persistent_kernel<N, VS, true>), dim3(a.grid), dim3(block), lds, a.stream, a.plan,
@@ -753,6 +779,7 @@ static hipError_t launch_n(const LaunchArgs &a) {
             hipLaunchKernelGGL((plain_kernel<N, VS, false>), dim3((unsigned)grid), dim3(block), lds, a.stream,
                                a.plan, recs, a.num, a.counts, a.steps);
     }
+    if (a.ev_stop) (void)hipEventRecord(a.ev_stop, a.stream);
     return hipGetLastError();
 }
 
@@ -816,6 +843,17 @@ hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
     hipLaunchKernelGGL(zero_u64, dim3(grid), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_weighted(const uint64_t *counts, const uint32_t *mult, int64_t num, uint64_t *out,
+                                  hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(zero_one, dim3(1), dim3(64), 0, stream, out);
+    if (num > 0) {
+        const unsigned grid = (unsigned)((num + 255) / 256 < 2048 ? (num + 255) / 256 : 2048);
+        hipLaunchKernelGGL(reduce_weighted, dim3(grid), dim3(256), 0, stream, counts, mult, num, out);
+    }
     return hipGetLastError();
 }
 

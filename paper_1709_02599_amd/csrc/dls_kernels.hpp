@@ -61,12 +61,16 @@ struct LaunchArgs {
     int64_t item_cap;
     Tuning tune;
     hipStream_t stream;
+    hipEvent_t ev_start;   // recorded around the search kernel when non-null
+    hipEvent_t ev_stop;
 };
 
 uint32_t make_desc(int n, bool vs, int i, int j);
 hipError_t launch(const LaunchArgs &a);
 hipError_t launch_valu_probe(int blocks, int iters, uint32_t *sink, hipStream_t stream);
 hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream);
+hipError_t launch_reduce_weighted(const uint64_t *counts, const uint32_t *mult, int64_t num, uint64_t *out,
+                                  hipStream_t stream);
 size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent);
 
 }  // namespace dlsk

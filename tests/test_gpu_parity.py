@@ -13,7 +13,8 @@ from tests.gpu_helpers import gpu_counts, weighted_total
 
 pytestmark = pytest.mark.gpu
 
-dls = pytest.importorskip("paper_1709_02599_amd")
+from tests.needs_lib import load as _load_dls  # noqa: E402
+dls = _load_dls()
 import dls_workloads as workloads  # noqa: E402
 
 E = 0xFF

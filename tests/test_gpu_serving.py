@@ -8,7 +8,8 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-dls = pytest.importorskip("paper_1709_02599_amd")
+from tests.needs_lib import load as _load_dls  # noqa: E402
+dls = _load_dls()
 import dls_workloads  # noqa: E402
 
 

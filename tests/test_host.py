@@ -11,7 +11,8 @@ import pytest
 import oracle
 from tests import golden_io
 
-dls = pytest.importorskip("paper_1709_02599_amd")
+from tests.needs_lib import load as _load_dls  # noqa: E402
+dls = _load_dls()
 import dls_workloads as workloads  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -63,6 +64,30 @@ def test_order_matches_oracle_random_patterns():
         got = dls.dls_order(n, int(vs), assigned)
         want = oracle.fill_order(n, np.flatnonzero(assigned).tolist(), vs=vs)
         assert got == want, (n, vs)
+
+
+@pytest.mark.parametrize("n", [4, 5, 7, 8, 9])
+@pytest.mark.parametrize("flags", [0, 1, 2])
+def test_order_variants_are_valid_orders(n, flags):
+    assigned = np.zeros(n * n, dtype=np.uint8)
+    assigned[:n] = 1
+    paper = dls.dls_order(n, flags, assigned)
+    assert dls.dls_order_variant(n, flags, assigned, 0) == paper
+    hc = set(oracle.hourglass_cells(n))
+    orders = set()
+    for v in range(8):
+        o = dls.dls_order_variant(n, flags, assigned, v)
+        # the same cells as the paper's order, each once
+        assert sorted(o) == sorted(paper), v
+        if flags & 2:
+            # the hourglass comes first whatever the variant
+            assert set(o[:len(hc)]) == hc, v
+        orders.add(tuple(o))
+    if n >= 7:
+        assert len(orders) > 1
+    for bad in (-1, 8):
+        with pytest.raises(dls.DLSError):
+            dls.dls_order_variant(n, flags, assigned, bad)
 
 
 # --------------------------------------------------------------------------
