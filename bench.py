@@ -59,23 +59,25 @@ OPS_PER_DOWN_STEP = 12
 OPS_PER_TASK = 3
 
 
-def tuned_launch(dls, torch):
-    """Launch settings for the order-8 workload from the autotuner's cache,
-    or the library defaults when it has not been tuned on this GPU."""
+LAUNCH_FIELDS = ("block", "refill_every", "order_variant", "expand_target", "chunk_min", "steal_depth")
+
+
+def tuned_launch(n, flags, workload):
+    """Launch settings for a workload from the autotuner's cache, or the
+    library defaults when it has not been tuned on this GPU."""
     try:
         from paper_1709_02599_amd import autotune
-        b = autotune.best(8, 0, "order8-symbreak-row1")
+        b = autotune.best(n, flags, workload)
     except Exception:
         b = None
     if not b:
         return {}
-    return {k: b[k] for k in ("block", "refill_every", "order_variant") if k in b}
+    return {k: b[k] for k in LAUNCH_FIELDS if k in b}
 
 
 def launch_of(dls, settings, time_kernel=0):
-    return dls.DlsLaunch(block=settings.get("block", 0), blocks_per_cu=0, steal_depth=0,
-                         refill_every=settings.get("refill_every", 0),
-                         order_variant=settings.get("order_variant", 0), time_kernel=time_kernel)
+    kw = {k: int(settings.get(k, 0)) for k in LAUNCH_FIELDS}
+    return dls.DlsLaunch(blocks_per_cu=0, time_kernel=time_kernel, **kw)
 
 
 def parse():
@@ -142,7 +144,7 @@ def main():
     d_steps = torch.zeros(1, dtype=torch.int64, device=dev)
     d_total = torch.zeros(1, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
-    tuned = tuned_launch(dls, torch)
+    tuned = tuned_launch(8, 0, "order8-symbreak-row1")
 
     def run(flags, launch):
         dls.dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_status, stream, launch)
@@ -211,25 +213,38 @@ def main():
                        "dls_per_s": leaves / (wall / args.steps),
                        "exact": int(tot.item()) == ORDER8_FIXED and int(d_status.item()) == 0}
     del step
-    # order 7, split at the diagonals: a small batch where launch cost matters
-    pre7, mult7 = dls.dls_split(7, 0, 11)
+    # order 7, split at the diagonals: 2016 prefixes, far fewer than lanes
+    pre7, _ = dls.dls_split(7, 0, 11)
     d7 = torch.from_numpy(pre7).to(dev)
     c7 = torch.zeros(len(pre7), dtype=torch.int64, device=dev)
     pat7 = (pre7[0] != 0xFF).astype(np.uint8)
-    step7 = CountStep(7, 0, pat7, d7, len(pre7), c7, d_status).capture()
+    tuned7 = tuned_launch(7, 0, "order7-diag11")
     reps7 = 50
-    totals7 = {}
-    for name, fn in (("eager", step7.eager), ("graph", step7.replay)):
-        fn()
+    order7 = {"prefixes": len(pre7), "launch": tuned7 or "library defaults"}
+    for name, flags, settings in (("persistent", 0, tuned7), ("plain", dls.DLS_PLAIN, {})):
+        dls.dls_count_async_ex(7, flags, pat7, d7, len(pre7), c7, d_status, stream, launch_of(dls, settings))
         torch.cuda.synchronize()
+        timed7 = launch_of(dls, settings, time_kernel=1)
         t_start = time.perf_counter()
         for _ in range(reps7):
-            tot = fn()
+            dls.dls_count_async_ex(7, flags, pat7, d7, len(pre7), c7, d_status, stream, timed7)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
-        totals7[name] = int(tot.item())
-        graph["order7_" + name] = {"us_per_step": 1e6 * wall / reps7, "prefixes": len(pre7),
-                                   "count": totals7[name], "exact": totals7[name] == totals7.get("eager")}
+        kms, _ = dls.dls_kernel_time_ms(stream)
+        order7[name] = {"kernel_us": 1e3 * kms, "us_per_step": 1e6 * wall / reps7,
+                        "count": int(c7.sum().item())}
+    step7 = CountStep(7, 0, pat7, d7, len(pre7), c7, d_status, None, launch_of(dls, tuned7)).capture()
+    step7.replay()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(reps7):
+        tot = step7.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    order7["persistent_graph_us_per_step"] = 1e6 * wall / reps7
+    order7["speedup_persistent_vs_plain"] = order7["plain"]["kernel_us"] / order7["persistent"]["kernel_us"]
+    order7["exact"] = (int(tot.item()) == order7["persistent"]["count"] == order7["plain"]["count"]
+                       and int(d_status.item()) == 0)
     del step7, d7, c7
 
     # ---------------- sustained variant: the full count, no symmetry breaking ----------------
@@ -316,13 +331,15 @@ def main():
                          "kernel_ms": results["plain"]["kernel_ms"]},
         "persistent_kernel_ms": p["kernel_ms"],
         "graph": graph,
+        "order7_diag_split": order7,
         "speedup_persistent_vs_plain": results["plain"]["ms_per_step"] / p["ms_per_step"],
         "effective_counted_per_s": weighted / (p["ms_per_step"] * 1e-3),
         "dfs_steps_per_launch": total_steps,
         "alg_ops_per_launch": alg_ops,
         "split_seconds_host": split_s,
         "sustained_full_count": sustained,
-        "exact": all(r["exact"] for r in results.values()) and all(g["exact"] for g in graph.values()),
+        "exact": (all(r["exact"] for r in results.values()) and all(g["exact"] for g in graph.values())
+                  and order7["exact"]),
     }
     print(json.dumps(line))
 

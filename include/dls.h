@@ -158,8 +158,18 @@ typedef struct {
     int order_variant;  /* fill-order variant (see dls_order_variant); 0 =
                            the rule of Sec. 2.3.  Counts never depend on it. */
     int time_kernel;    /* nonzero: record a HIP event pair around the
-                           search kernel on the launch stream (not under
+                           search kernels on the launch stream (not under
                            graph capture); read with dls_kernel_time_ms  */
+    int expand_target;  /* persistent kernel: a batch of fewer tasks than
+                           this is first deepened on the device, one level
+                           per pass, until it has this many tasks (the split
+                           of Sec. 5.2 done breadth-first on the GPU).
+                           0 = default (the number of lanes launched),
+                           negative = off; at most 2^28.  Uses 4x this many
+                           task slots of device memory per stream.        */
+    int chunk_min;      /* persistent kernel: smallest number of tasks a
+                           wave takes from the static queue at once
+                           (0 = default 8; at most 65536)                  */
 } dls_launch;
 
 /* Mean duration in milliseconds of the search kernels launched with

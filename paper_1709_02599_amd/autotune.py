@@ -68,15 +68,24 @@ def best(n: int, flags: int, workload: str, arch: Optional[str] = None) -> Optio
     return entry["best"] if entry else None
 
 
-def time_launch(n: int, flags: int, pattern, d_pre, num: int, d_cnt, d_st, stream, launch: DlsLaunch,
+FIELDS = ("block", "blocks_per_cu", "steal_depth", "refill_every", "order_variant", "time_kernel",
+          "expand_target", "chunk_min")
+
+
+def _launch(settings: dict, time_kernel: int = 0) -> DlsLaunch:
+    kw = {k: int(settings.get(k, 0)) for k in FIELDS}
+    kw["time_kernel"] = time_kernel
+    return DlsLaunch(**kw)
+
+
+def time_launch(n: int, flags: int, pattern, d_pre, num: int, d_cnt, d_st, stream, settings: dict,
                 reps: int = 3):
-    """Mean duration (ms) of the search kernel over `reps` launches, measured
+    """Mean duration (ms) of the search kernels over `reps` launches, measured
     by the library's event pairs on the launch stream, plus a digest of the
     counts of the last launch and the device status."""
     import torch
-    dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, launch)   # warm-up
-    timed = DlsLaunch(launch.block, launch.blocks_per_cu, launch.steal_depth, launch.refill_every,
-                      launch.order_variant, 1)
+    dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, _launch(settings))  # warm-up
+    timed = _launch(settings, 1)
     for _ in range(reps):
         dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, timed)
     torch.cuda.synchronize()
@@ -87,10 +96,13 @@ def time_launch(n: int, flags: int, pattern, d_pre, num: int, d_cnt, d_st, strea
     return ms, digest, int(d_st.item())
 
 
-def tune(n: int, flags: int, prefixes: np.ndarray, workload: str,
-         variants: Iterable[int] = VARIANTS, blocks: Iterable[int] = BLOCKS,
-         refills: Iterable[int] = REFILLS, reps: int = 3, save: bool = True) -> dict:
+def tune(n: int, flags: int, prefixes: np.ndarray, workload: str, space: Optional[Dict[str, Iterable]] = None,
+         default: Optional[dict] = None, reps: int = 3, save: bool = True) -> dict:
+    """Time every combination of the launch settings in `space` (field ->
+    candidate values); all must give identical counts.  Keeps the fastest."""
     import torch
+    space = space or {"order_variant": VARIANTS, "block": BLOCKS, "refill_every": REFILLS}
+    default = default or {"order_variant": 0, "block": 256, "refill_every": 32}
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     pre = np.ascontiguousarray(prefixes, dtype=np.uint8)
@@ -99,26 +111,27 @@ def tune(n: int, flags: int, prefixes: np.ndarray, workload: str,
     d_pre = torch.from_numpy(pre).to(dev)
     d_cnt = torch.zeros(num, dtype=torch.int64, device=dev)
     d_st = torch.zeros(1, dtype=torch.int32, device=dev)
+    keys = list(space)
     table: List[dict] = []
     ref = None
-    for v, blk, rf in itertools.product(variants, blocks, refills):
-        launch = DlsLaunch(block=blk, blocks_per_cu=0, steal_depth=0, refill_every=rf, order_variant=v)
-        ms, digest, st = time_launch(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, launch, reps)
+    for values in itertools.product(*(space[k] for k in keys)):
+        settings = dict(zip(keys, values))
+        ms, digest, st = time_launch(n, flags, pattern, d_pre, num, d_cnt, d_st, stream, settings, reps)
         if st:
-            raise RuntimeError(f"device status {st} for variant {v}, block {blk}, refill {rf}")
+            raise RuntimeError(f"device status {st} for {settings}")
         if ref is None:
             ref = digest
         elif digest != ref:
-            raise RuntimeError(f"counts differ for variant {v}, block {blk}, refill {rf}")
-        table.append({"order_variant": v, "block": blk, "refill_every": rf, "ms": ms})
+            raise RuntimeError(f"counts differ for {settings}")
+        table.append({**settings, "ms": ms})
     # the plain kernel under the paper's order, for reference
     plain_ms, digest, _ = time_launch(n, flags | DLS_PLAIN, pattern, d_pre, num, d_cnt, d_st, stream,
-                                      DlsLaunch(block=256), reps)
+                                      {"block": 256}, reps)
     if digest != ref:
         raise RuntimeError("plain kernel counts differ")
     table.sort(key=lambda r: r["ms"])
-    default = [r for r in table if r["order_variant"] == 0 and r["block"] == 256 and r["refill_every"] == 32]
-    result = {"best": table[0], "default": default[0] if default else None, "plain_ms": plain_ms,
+    dflt = [r for r in table if all(r.get(k) == v for k, v in default.items())]
+    result = {"best": table[0], "default": dflt[0] if dflt else None, "plain_ms": plain_ms,
               "candidates": len(table), "table": table[:12], "prefixes": num,
               "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
     if save:
@@ -146,9 +159,8 @@ def tune_depth(n: int, flags: int, depths: Iterable[int], workload: str, launch:
         d_pre = torch.from_numpy(pre).to(dev)
         d_cnt = torch.zeros(num, dtype=torch.int64, device=dev)
         d_st = torch.zeros(1, dtype=torch.int32, device=dev)
-        lc = DlsLaunch(**(launch or {}))
         kflags = flags & ~DLS_SYMBREAK & 1
-        ms, _, st = time_launch(n, kflags, pattern, d_pre, num, d_cnt, d_st, stream, lc, reps)
+        ms, _, st = time_launch(n, kflags, pattern, d_pre, num, d_cnt, d_st, stream, launch or {}, reps)
         tot = int((d_cnt * torch.from_numpy(mult.astype(np.int64)).to(dev)).sum().item())
         if total_ref is None:
             total_ref = tot
@@ -168,19 +180,36 @@ def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--only", default="", help="comma-separated workload names")
     args = ap.parse_args(argv)
-    pre, mult = dls_split(8, DLS_SYMBREAK, 26)
-    r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps)
-    print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
-                      "plain_ms": r["plain_ms"]}), flush=True)
-    d = tune_depth(8, DLS_SYMBREAK, (20, 22, 24, 26, 27, 28), "order8-symbreak",
-                   launch={k: r["best"][k] for k in ("block", "refill_every", "order_variant")},
-                   reps=args.reps)
-    print(json.dumps({"workload": "order8-symbreak", "depths": d["table"]}), flush=True)
-    spre, _ = dls_split(8, 0, 14)
-    s = tune(8, 0, spre, "order8-diag14", variants=(0, 1, 2, 3, 6), blocks=(256,), refills=(32,),
-             reps=1)
-    print(json.dumps({"workload": "order8-diag14", "best": s["best"], "default": s["default"]}), flush=True)
+    only = set(filter(None, args.only.split(",")))
+
+    def want(name):
+        return not only or name in only
+
+    if want("order8-symbreak-row1"):
+        pre, mult = dls_split(8, DLS_SYMBREAK, 26)
+        r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps)
+        print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
+                          "plain_ms": r["plain_ms"]}), flush=True)
+        d = tune_depth(8, DLS_SYMBREAK, (20, 22, 24, 26, 27, 28), "order8-symbreak",
+                       launch={k: r["best"][k] for k in ("block", "refill_every", "order_variant")},
+                       reps=args.reps)
+        print(json.dumps({"workload": "order8-symbreak", "depths": d["table"]}), flush=True)
+    if want("order7-diag11"):
+        # order 7 split at the diagonals: a batch far smaller than the lanes
+        pre, _ = dls_split(7, 0, 11)
+        r = tune(7, 0, pre, "order7-diag11",
+                 space={"expand_target": (0, -1, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18),
+                        "chunk_min": (0, 1, 4, 16, 64), "refill_every": (0, 16)},
+                 default={"expand_target": 0, "chunk_min": 0, "refill_every": 0}, reps=args.reps)
+        print(json.dumps({"workload": "order7-diag11", "best": r["best"], "plain_ms": r["plain_ms"],
+                          "top": r["table"][:6]}), flush=True)
+    if want("order8-diag14"):
+        spre, _ = dls_split(8, 0, 14)
+        s = tune(8, 0, spre, "order8-diag14", space={"order_variant": (0, 1, 2, 3, 5, 6)},
+                 default={"order_variant": 0}, reps=1)
+        print(json.dumps({"workload": "order8-diag14", "best": s["best"], "default": s["default"]}), flush=True)
 
 
 if __name__ == "__main__":

@@ -87,6 +87,14 @@ struct QueueSlot {
     // search-kernel timing: one event pair per timed launch since the last query
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     size_t ev_used = 0;
+    // breadth-first expansion of small batches (allocated on first use)
+    dlsk::Expand *ex = nullptr;      // two states
+    uint32_t *eblk = nullptr;        // per-workgroup tallies
+    void *ebuf[2] = {nullptr, nullptr};
+    uint32_t *eorig[2] = {nullptr, nullptr};
+    uint64_t *tcounts = nullptr;
+    size_t ebuf_bytes = 0;
+    int64_t ecap = 0;
 };
 
 constexpr size_t kMaxTimed = 1 << 16;
@@ -168,6 +176,45 @@ int queue_slot(DeviceState *ds, void *stream, size_t records_bytes, QueueSlot **
         q.records_bytes = want;
     }
     *out = &q;
+    return DLS_OK;
+}
+
+// Expansion buffers of a stream for `ecap` tasks of `rb` bytes each.
+int expand_buffers(void *stream, QueueSlot *q, int64_t ecap, size_t rb) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    const size_t want = (size_t)ecap * rb;
+    if (q->ex && q->ecap >= ecap && q->ebuf_bytes >= want) return DLS_OK;
+    if (capturing(stream)) return DLS_ECAPTURE;
+    if (q->ex) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+        for (void *p : {(void *)q->ebuf[0], (void *)q->ebuf[1], (void *)q->eorig[0], (void *)q->eorig[1],
+                        (void *)q->tcounts})
+            if (p) (void)hipFree(p);
+        q->ebuf[0] = q->ebuf[1] = nullptr;
+        q->eorig[0] = q->eorig[1] = nullptr;
+        q->tcounts = nullptr;
+        q->ebuf_bytes = 0;
+        q->ecap = 0;
+    } else {
+        if (hipMalloc((void **)&q->ex, 2 * sizeof(dlsk::Expand)) != hipSuccess) {
+            q->ex = nullptr;
+            return DLS_ENOMEM;
+        }
+        if (hipMalloc((void **)&q->eblk, sizeof(uint32_t) * dlsk::kExBlocks) != hipSuccess) {
+            (void)hipFree(q->ex);
+            q->ex = nullptr;
+            q->eblk = nullptr;
+            return DLS_ENOMEM;
+        }
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (hipMalloc(&q->ebuf[k], want) != hipSuccess) return DLS_ENOMEM;
+        if (hipMalloc((void **)&q->eorig[k], sizeof(uint32_t) * (size_t)ecap) != hipSuccess) return DLS_ENOMEM;
+    }
+    if (hipMalloc((void **)&q->tcounts, sizeof(uint64_t) * (size_t)ecap) != hipSuccess) return DLS_ENOMEM;
+    q->ebuf_bytes = want;
+    q->ecap = ecap;
     return DLS_OK;
 }
 
@@ -260,13 +307,38 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
         // the batch is too small to keep every lane busy (e.g. one big prefix).
         // Inside a wave, idle lanes always take work from busy ones.
         const int64_t lanes = (int64_t)a.grid * block;
-        int sd = num < lanes / 4 ? std::max(8, a.plan.nlev / 3) : 0;
+        // a batch with fewer tasks than lanes is first deepened on the device
+        int64_t et = lanes;
+        if (launch && launch->expand_target) et = launch->expand_target < 0 ? 0 : launch->expand_target;
+        if (et > (1 << 28)) return DLS_EINVAL;
+        const bool expand = et > 0 && num < et && a.plan.nlev >= 3;
+        // Global donation (work handed between waves through the device
+        // queue) is for batches too small to keep the lanes busy that are not
+        // deepened first, e.g. a few huge prefixes with the expansion off.
+        int sd = (!expand && num < lanes / 4) ? std::max(8, a.plan.nlev / 3) : 0;
         if (launch && launch->steal_depth) sd = launch->steal_depth < 0 ? 0 : launch->steal_depth;
         a.tune.steal_depth = sd;
         a.tune.refill_min = 8;
         a.tune.donate_max = 2;
         a.tune.donate_low = 256;
         a.tune.tail_poll = 4;
+        a.tune.chunk_min = (launch && launch->chunk_min) ? launch->chunk_min : 8;
+        if (a.tune.chunk_min < 1 || a.tune.chunk_min > 65536) return DLS_EINVAL;
+        if (expand) {
+            const int64_t ecap = 4 * et;
+            rc = expand_buffers(stream, qs, ecap, dlsk::record_bytes(n, vs));
+            if (rc) return rc;
+            a.ex = qs->ex;
+            a.eblk = qs->eblk;
+            a.ebuf[0] = qs->ebuf[0];
+            a.ebuf[1] = qs->ebuf[1];
+            a.eorig[0] = qs->eorig[0];
+            a.eorig[1] = qs->eorig[1];
+            a.tcounts = qs->tcounts;
+            a.ecap = ecap;
+            a.etarget = et;
+            a.epasses = std::min(a.plan.nlev - 2, 16);
+        }
     }
     hipError_t e = dlsk::launch(a);
     return e == hipSuccess ? DLS_OK : hip_fail(e, DLS_EDEVICE);

@@ -383,8 +383,14 @@ template <int N, bool VS, bool STATS>
 __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const Rec<N, VS> *recs, int64_t num,
                                                           uint64_t *counts, uint32_t *status, uint64_t *steps,
                                                           Ctrl *ctrl, Rec<N, VS> *items, uint32_t *ready,
-                                                          int64_t item_cap, Tuning tune) {
+                                                          int64_t item_cap, Tuning tune, const Expand *ex) {
     using S = StackT<N>;
+    if (ex) {
+        // the batch as the expansion passes left it
+        recs = reinterpret_cast<const Rec<N, VS> *>(ex->recs);
+        num = ex->num;
+        counts = ex->counts;
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *sdesc = reinterpret_cast<uint32_t *>(smem);
     const int nlev = plan.nlev;
@@ -403,9 +409,12 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     const int lim = tune.steal_depth > 0 ? nlev - tune.steal_depth : 0;
     const uint64_t total_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
 
+    // Work moves between waves only with global donation; without it a wave
+    // whose lanes are all idle once the static queue is empty just leaves.
+    const bool global = cap > 0 && lim > 0;
     // this wave counts as busy from its start until it finds no work anywhere
-    if (lane == 0) atomicAdd((unsigned long long *)&ctrl->busy, 1ull);
-    bool marked = true;
+    if (global && lane == 0) atomicAdd((unsigned long long *)&ctrl->busy, 1ull);
+    bool marked = global;
 
     Lane<N, VS> L;
     L.cand = 0u;
@@ -440,7 +449,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
             // has a single writer: the lane stores its running count (the last
             // store is the final one) instead of adding atomically.  Tasks come
             // from a wave-private range refilled with a guided chunk
-            // (remaining / (2 * waves)) by one atomic on ctrl->head.  Every
+            // (remaining / (2 * waves), at least chunk_min) by one atomic on
+            // ctrl->head.  Every
             // lane issues the same memory operations (one record load, then
             // one count store), so the wait below covers the loads only.
             if (want && (__popcll(want) >= tune.refill_min || want == ~0ull)) {
@@ -454,7 +464,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                     if (cb >= ce) {
                         const uint64_t rem = (uint64_t)num > ce ? (uint64_t)num - ce : 0;
                         uint64_t sz = rem / (2 * total_waves);
-                        sz = sz < 64 ? 64 : (sz > 65536 ? 65536 : sz);
+                        const uint64_t lo = (uint64_t)tune.chunk_min;
+                        sz = sz < lo ? lo : (sz > 65536 ? 65536 : sz);
                         uint64_t base = 0;
                         if (lane == leader)
                             base = atomicAdd((unsigned long long *)&ctrl->head, (unsigned long long)sz);
@@ -534,6 +545,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                 __builtin_amdgcn_wave_barrier();
                 want = __ballot(!has);
             }
+        }
+        if (!global) {
+            if (want == ~0ull) break;
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            continue;
         }
         // the queue state is read once every few passes (or when idle)
         ++tick;
@@ -674,6 +690,316 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     if (STATS && steps) atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
 }
 
+// ---------------------------------------------------------------------------
+// breadth-first expansion of small batches
+// ---------------------------------------------------------------------------
+// A batch with fewer tasks than lanes leaves most of the GPU idle.  Before the
+// persistent kernel runs, passes replace every task by its children one level
+// deeper (the split of Sec. 5.2, done on the device), until the batch has
+// `target` tasks or the next level would not fit the buffers.  Children on
+// the last level are counted at once; dead children are dropped.
+//
+// A pass is two kernels over kExBlocks workgroups, each taking an equal
+// contiguous share of the current tasks: ex_tally stores the number of live
+// children of each share, ex_write derives every share's output offset from
+// those tallies and writes the children in order.  No atomics or fences
+// place the output, so tasks stay sorted by prefix.  The pass state is double
+// buffered (pass p reads state p & 1 and workgroup 0 writes state (p+1) & 1),
+// so every decision is taken on the device and the sequence needs no host
+// round trip: it can be captured in a graph.
+//
+// Expanded tasks have their own count slots (tcounts), zeroed when the task
+// is written (the search adds to a slot atomically when it takes a task at
+// the end of the static queue) and summed into the prefixes' counts by
+// ex_scatter at the end.
+
+__global__ void ex_init(Expand *E, const void *recs, int64_t num, uint64_t *counts) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Expand e;
+        e.recs = recs;
+        e.num = num;
+        e.counts = counts;
+        e.orig = nullptr;
+        e.want = e.want_next = e.nout = 0;
+        e.cur = 0;
+        e.stop = num == 0;
+        e.done = e.pad = 0;
+        E[0] = e;
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, o);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), o);
+        x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Inclusive sum over the workgroup (256 threads, 4 waves); *total gets the
+// workgroup's sum.  Uses part[4] of LDS; every thread must call it.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *part, uint32_t *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) part[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t q = part[k];
+        before += k < w ? q : 0u;
+        all += q;
+    }
+    __syncthreads();  // part[] may be reused right after
+    *total = all;
+    return x + before;
+}
+
+// Adds values to ucounts[orig] for (orig, value) pairs that a wave visits in
+// increasing position order.  Tasks are sorted by prefix, so the values of
+// one prefix are summed in registers and added with one atomic per run.  The
+// run state is wave-uniform.
+struct RunSum {
+    uint32_t o = 0xFFFFFFFFu;
+    uint64_t v = 0;
+
+    __device__ __forceinline__ void add(uint32_t orig, uint64_t val, uint64_t *ucounts) {
+        const int lane = threadIdx.x & 63;
+        uint64_t pend = __ballot(val != 0);
+        while (pend) {
+            const int ld = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t g = (uint32_t)__shfl((int)orig, ld);
+            const bool in = ((pend >> lane) & 1ull) && orig == g;
+            const uint64_t grp = __ballot(in);
+            const uint64_t sum = wave_sum64(in ? val : 0ull);
+            if (g != o) {
+                if (lane == 0 && v) atomicAdd((unsigned long long *)&ucounts[o], (unsigned long long)v);
+                o = g;
+                v = 0;
+            }
+            v += sum;
+            pend &= ~grp;
+        }
+    }
+
+    // one atomic per run left in the workgroup's four waves (runs of equal
+    // prefixes merged); every thread must call it
+    __device__ __forceinline__ void flush(uint64_t *ucounts, uint32_t *so, uint64_t *sv) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if (lane == 0) {
+            so[w] = o;
+            sv[w] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t co = 0xFFFFFFFFu;
+            uint64_t cv = 0;
+            for (int k = 0; k < 4; ++k) {
+                if (!sv[k]) continue;
+                if (so[k] != co) {
+                    if (cv) atomicAdd((unsigned long long *)&ucounts[co], (unsigned long long)cv);
+                    co = so[k];
+                    cv = 0;
+                }
+                cv += sv[k];
+            }
+            if (cv) atomicAdd((unsigned long long *)&ucounts[co], (unsigned long long)cv);
+        }
+        v = 0;
+    }
+};
+
+// Children of one task: how many are live (to be written) and, when they sit
+// on the last level, their candidate counts (squares completed at once).
+template <int N, bool VS>
+struct Kids {
+    Lane<N, VS> L;
+    uint32_t cand = 0u, lvl = kNone, kids = 0u, orig = 0u;
+    uint64_t leaves = 0u;
+
+    __device__ __forceinline__ void load(const Rec<N, VS> *in, const uint32_t *iorig, int64_t i,
+                                         const uint32_t *sdesc, int last) {
+        const Rec<N, VS> r = in[i];
+        lvl = r.cl >> 16;
+        if (lvl == kNone) return;
+        orig = iorig ? iorig[i] : (uint32_t)i;
+        if ((int)lvl >= last) {  // not produced by prep or by a pass; counted as the search would
+            leaves = (uint64_t)__builtin_popcount(r.cl & 0xFFFFu);
+            lvl = kNone;
+            return;
+        }
+        L.from_rec(r, sdesc, last);
+        cand = r.cl & 0xFFFFu;
+        const uint32_t dc = sdesc[lvl], dn = sdesc[lvl + 1];
+        for (uint32_t c = cand; c; c &= c - 1u) {
+            Lane<N, VS> T = L;
+            T.toggle(dc, c & (0u - c));
+            const uint32_t nc = T.cands(dn);
+            if ((int)lvl + 1 == last) leaves += (uint64_t)__builtin_popcount(nc);
+            else kids += nc ? 1u : 0u;
+        }
+    }
+};
+
+__device__ __forceinline__ void ex_share(int64_t num, int64_t *b0, int64_t *b1) {
+    const int64_t per = (num + kExBlocks - 1) / kExBlocks;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    *b0 = lo < num ? lo : num;
+    *b1 = lo + per < num ? lo + per : num;
+}
+
+template <int N, bool VS>
+__global__ void __launch_bounds__(256) ex_tally(const Plan plan, const Expand *E2, int pass, uint32_t *blk) {
+    __shared__ uint32_t sdesc[kMaxLevels];
+    __shared__ uint32_t part[4];
+    const Expand *E = &E2[pass & 1];
+    if (E->stop) return;
+    const int nlev = plan.nlev;
+    for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
+    __syncthreads();
+    const Rec<N, VS> *in = reinterpret_cast<const Rec<N, VS> *>(E->recs);
+    const uint32_t *iorig = E->orig;
+    int64_t b0, b1;
+    ex_share(E->num, &b0, &b1);
+    uint32_t mine = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        Kids<N, VS> k;
+        k.load(in, iorig, i, sdesc, nlev - 1);
+        mine += k.kids;
+    }
+    uint32_t total = 0;
+    block_scan(mine, part, &total);
+    if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+template <int N, bool VS>
+__global__ void __launch_bounds__(256) ex_write(const Plan plan, Expand *E2, int pass, const uint32_t *blk,
+                                                void *buf1, void *buf2, uint32_t *orig1, uint32_t *orig2,
+                                                uint64_t *ucounts, uint64_t *tcounts, uint32_t *status,
+                                                int64_t target, int64_t cap) {
+    using R = Rec<N, VS>;
+    static_assert(kExBlocks == 4 * 256, "each thread sums four tallies");
+    __shared__ uint32_t sdesc[kMaxLevels];
+    __shared__ uint32_t part[4];
+    __shared__ uint32_t so[4];
+    __shared__ uint64_t sv[4];
+    const Expand e = E2[pass & 1];
+    Expand *eo = &E2[(pass + 1) & 1];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (e.stop) {
+        if (lead) *eo = e;
+        return;
+    }
+    const int nlev = plan.nlev;
+    for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
+    // output offset of this share and the pass total, from the tallies
+    uint32_t t_all = 0, t_before = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t h = 4u * threadIdx.x + (uint32_t)k;
+        const uint32_t q = blk[h];
+        t_all += q;
+        t_before += h < blockIdx.x ? q : 0u;
+    }
+    uint32_t total = 0, base = 0;
+    block_scan(t_all, part, &total);
+    block_scan(t_before, part, &base);
+    const int cur = e.cur;
+    R *out = reinterpret_cast<R *>(cur == 1 ? buf2 : buf1);
+    uint32_t *oorig = cur == 1 ? orig2 : orig1;
+    const bool go = e.num < target && (int64_t)total <= cap;
+    if (lead) {
+        Expand n = e;
+        if (go) {
+            n.recs = out;
+            n.orig = oorig;
+            n.cur = cur == 1 ? 2 : 1;
+            n.num = total;
+            n.counts = tcounts;
+            n.stop = total == 0;
+        } else {
+            n.stop = 1;
+        }
+        *eo = n;
+    }
+    if (!go) return;
+    const R *in = reinterpret_cast<const R *>(e.recs);
+    const int last = nlev - 1;
+    int64_t b0, b1;
+    ex_share(e.num, &b0, &b1);
+    uint64_t run = base;
+    RunSum acc;
+    for (int64_t chunk = b0; chunk < b1; chunk += blockDim.x) {  // uniform per workgroup
+        const int64_t i = chunk + threadIdx.x;
+        Kids<N, VS> k;
+        if (i < b1) k.load(in, e.orig, i, sdesc, last);
+        uint32_t step = 0;
+        const uint32_t incl = block_scan(k.kids, part, &step);
+        uint64_t pos = run + (incl - k.kids);
+        run += step;
+        if (k.kids) {
+            const uint32_t dc = sdesc[k.lvl], dn = sdesc[k.lvl + 1];
+            for (uint32_t c = k.cand; c; c &= c - 1u) {
+                Lane<N, VS> T = k.L;
+                T.toggle(dc, c & (0u - c));
+                const uint32_t nc = T.cands(dn);
+                if (!nc) continue;
+                if (pos >= (uint64_t)cap) {  // cannot happen: the tallies bound the output
+                    if (status) atomicOr(status, 4u);
+                    break;
+                }
+                R o;
+#pragma unroll
+                for (int w = 0; w < Geo<N, VS>::WR; ++w) o.R[w] = T.R[w];
+#pragma unroll
+                for (int w = 0; w < Geo<N, VS>::WC; ++w) o.C[w] = T.C[w];
+                o.diag = T.md | (T.ad << 16);
+                o.cl = nc | ((k.lvl + 1u) << 16);
+                o.origin = (uint32_t)pos;
+                o.pad = 0;
+                out[pos] = o;
+                oorig[pos] = k.orig;
+                // the search may add to a task's slot before it stores one
+                tcounts[pos] = 0;
+                ++pos;
+            }
+        }
+        acc.add(k.orig, k.leaves, ucounts);
+    }
+    acc.flush(ucounts, so, sv);
+}
+
+// add the expanded tasks' counts to their prefixes
+__global__ void __launch_bounds__(256) ex_scatter(const Expand *E, uint64_t *ucounts) {
+    __shared__ uint32_t so[4];
+    __shared__ uint64_t sv[4];
+    const uint32_t *orig = E->orig;
+    if (!orig) return;  // nothing was expanded: the search wrote ucounts itself
+    const uint64_t *tc = E->counts;
+    int64_t b0, b1;
+    ex_share(E->num, &b0, &b1);
+    RunSum acc;
+    for (int64_t chunk = b0; chunk < b1; chunk += blockDim.x) {
+        const int64_t i = chunk + threadIdx.x;
+        const bool ok = i < b1;
+        acc.add(ok ? orig[i] : 0u, ok ? tc[i] : 0ull, ucounts);
+    }
+    acc.flush(ucounts, so, sv);
+}
+
 // ready flags of the slots the previous launch on this queue reserved (all
 // consumed after a normal end; cleared anyway in case that launch stopped
 // early)
@@ -764,12 +1090,28 @@ static hipError_t launch_n(const LaunchArgs &a) {
     if (a.ev_start) (void)hipEventRecord(a.ev_start, a.stream);
     if (a.persistent) {
         R *items = reinterpret_cast<R *>(a.items);
+        const bool expand = a.ex != nullptr && a.plan.nlev >= 3;
+        if (expand) {
+            hipLaunchKernelGGL(ex_init, dim3(1), dim3(64), 0, a.stream, a.ex, a.records, a.num, a.counts);
+            for (int p = 0; p < a.epasses; ++p) {
+                hipLaunchKernelGGL((ex_tally<N, VS>), dim3(kExBlocks), dim3(256), 0, a.stream, a.plan, a.ex, p,
+                                   a.eblk);
+                hipLaunchKernelGGL((ex_write<N, VS>), dim3(kExBlocks), dim3(256), 0, a.stream, a.plan, a.ex, p,
+                                   a.eblk, a.ebuf[0], a.ebuf[1], a.eorig[0], a.eorig[1], a.counts, a.tcounts,
+                                   a.status, a.etarget, a.ecap);
+            }
+        }
+        // the state after the last pass
+        const Expand *ex = expand ? a.ex + (a.epasses & 1) : nullptr;
         if (a.steps)
             hipLaunchKernelGGL((persistent_kernel<N, VS, true>), dim3(a.grid), dim3(block), lds, a.stream, a.plan,
-                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune);
+                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune,
+                               ex);
         else
             hipLaunchKernelGGL((persistent_kernel<N, VS, false>), dim3(a.grid), dim3(block), lds, a.stream, a.plan,
-                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune);
+                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune,
+                               ex);
+        if (expand) hipLaunchKernelGGL(ex_scatter, dim3(kExBlocks), dim3(256), 0, a.stream, ex, a.counts);
     } else {
         const int64_t grid = (a.num + block - 1) / block;
         if (a.steps)

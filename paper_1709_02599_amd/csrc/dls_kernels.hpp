@@ -18,15 +18,42 @@ struct Plan {
     int nlev;             // number of levels (cells the kernels fill)
 };
 
-// Work-queue control block of the persistent kernel (device memory).
+// Work-queue control block of the persistent kernel (device memory).  Each
+// field sits on its own 128-byte line: idle waves poll some of them while
+// busy waves update others.
 struct Ctrl {
-    uint64_t head;         // next static task
-    uint64_t dq_reserve;   // donated slots reserved by producers
-    uint64_t dq_head;      // donated slots taken by consumers
-    uint64_t busy;         // waves that may still hold or create work
-    uint64_t sink;         // count target of lanes that have not had a task yet
-    uint64_t hungry;       // idle poller waves waiting for donated work
-    uint64_t pad[2];
+    uint64_t head;          // next static task
+    uint64_t pad0[15];
+    uint64_t dq_reserve;    // donated slots reserved by producers
+    uint64_t pad1[15];
+    uint64_t dq_head;       // donated slots taken by consumers
+    uint64_t pad2[15];
+    uint64_t busy;          // waves that may still hold or create work
+    uint64_t pad3[15];
+    uint64_t hungry;        // idle poller waves waiting for donated work
+    uint64_t pad4[15];
+    uint64_t sink;          // count target of lanes that have not had a task yet
+    uint64_t pad5[15];
+};
+
+// Workgroups of each breadth-first expansion kernel.
+constexpr int kExBlocks = 1024;
+
+// Device-side state of the breadth-first expansion that deepens a batch too
+// small to occupy the GPU before the persistent kernel runs (device memory,
+// two of them: pass p reads state p & 1 and writes state (p + 1) & 1).
+struct Expand {
+    const void *recs;       // current task records
+    int64_t num;            // their number
+    uint64_t *counts;       // per-task counts written by the search kernel
+    const uint32_t *orig;   // task -> prefix index (nullptr: identity)
+    uint64_t want;          // sum of candidate counts of the current set
+    uint64_t want_next;     // the same for the set being written
+    uint64_t nout;          // records written by the pass in progress
+    int32_t cur;            // buffer holding the current set: 0 prep, 1 or 2
+    int32_t stop;           // nonzero: expansion finished
+    uint32_t done;          // workgroups of the pass in progress that finished
+    uint32_t pad;
 };
 
 struct Tuning {
@@ -36,6 +63,7 @@ struct Tuning {
     int donate_max;    // donations per wave per queue visit
     int donate_low;    // donate while fewer donated tasks than this are queued
     int tail_poll;     // tail: read the queue state every tail_poll passes (power of 2)
+    int chunk_min;     // smallest static chunk a wave takes from the queue
 };
 
 // Size in bytes of one task record (packed masks of a partial square plus
@@ -61,8 +89,18 @@ struct LaunchArgs {
     int64_t item_cap;
     Tuning tune;
     hipStream_t stream;
-    hipEvent_t ev_start;   // recorded around the search kernel when non-null
+    hipEvent_t ev_start;   // recorded around the search kernels when non-null
     hipEvent_t ev_stop;
+    // breadth-first expansion of small batches (persistent kernel only;
+    // off when ex == nullptr)
+    Expand *ex;            // two states
+    uint32_t *eblk;        // kExBlocks per-workgroup tallies
+    void *ebuf[2];         // ecap task records each
+    uint32_t *eorig[2];    // ecap prefix indices each
+    uint64_t *tcounts;     // ecap per-task counts
+    int64_t ecap;
+    int64_t etarget;       // expand while fewer tasks than this
+    int epasses;           // expansion passes (each one level deeper)
 };
 
 uint32_t make_desc(int n, bool vs, int i, int j);

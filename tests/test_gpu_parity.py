@@ -108,6 +108,64 @@ def test_persistent_single_heavy_prefix_is_shared_out():
 
 
 # --------------------------------------------------------------------------
+# breadth-first expansion of small batches before the persistent kernel
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("target", [-1, 1, 7, 100, 5000, 0])   # off, tiny, ..., default
+def test_expansion_targets_order7(target):
+    pre, _ = dls.dls_split(7, 0, 11)
+    opre = _oracle_split(7, False, 11)
+    want = oracle.count_many(7, opre)
+    c, st = gpu_counts(dls, 7, 0, pre, launch={"expand_target": target})
+    assert st == 0 and np.array_equal(c, want), target
+
+
+@pytest.mark.parametrize("n,vs", [(4, False), (5, False), (6, False), (7, False), (6, True), (8, True)])
+@pytest.mark.parametrize("target", [3, 1000, 0])
+def test_expansion_single_prefix(n, vs, target):
+    # one prefix: every task after the passes shares its count slot
+    p = oracle.identity_prefix(n)
+    c, st = gpu_counts(dls, n, dls.DLS_VSYM if vs else 0, p[None], launch={"expand_target": target})
+    assert st == 0 and int(c[0]) == oracle.count(n, p, vs=vs)
+
+
+def test_expansion_mixed_dead_and_live_prefixes():
+    # every third prefix made inconsistent (a value repeated on the main
+    # diagonal), the others live: dead tasks drop out of the passes
+    pre, _ = dls.dls_split(7, 0, 11)
+    pre = pre.copy()
+    pre[::3, 2 * 7 + 2] = pre[::3, 1 * 7 + 1]
+    want = oracle.count_many(7, pre)
+    assert np.all(want[::3] == 0)
+    for target in (2, 50, 0):
+        c, st = gpu_counts(dls, 7, 0, pre, launch={"expand_target": target})
+        assert st == 0 and np.array_equal(c, want), target
+
+
+def test_expansion_reused_buffers_start_clean():
+    # the per-task count slots of one launch must not leak into the next on
+    # the same stream: alternate two batches several times
+    a, _ = dls.dls_split(7, 0, 8)
+    b, _ = dls.dls_split(7, 0, 11)
+    wa = oracle.count_many(7, _oracle_split(7, False, 8))
+    wb = oracle.count_many(7, _oracle_split(7, False, 11))
+    for rep in range(3):
+        for pre, want in ((a, wa), (b, wb)):
+            c, st = gpu_counts(dls, 7, 0, pre)
+            assert st == 0 and np.array_equal(c, want), (rep, len(pre))
+
+
+def test_expansion_capacity_bounds_a_pass():
+    # a target whose 4x capacity is below the next level's candidate count:
+    # the passes stop early and the search finishes the rest
+    pre, _ = dls.dls_split(7, 0, 8)
+    want = oracle.count_many(7, _oracle_split(7, False, 8))
+    for target in (len(pre) + 1, 2 * len(pre), 3 * len(pre)):
+        c, st = gpu_counts(dls, 7, 0, pre, launch={"expand_target": target})
+        assert st == 0 and np.array_equal(c, want), target
+
+
+# --------------------------------------------------------------------------
 # order 8 with symmetry breaking: canonical hourglasses + row 1
 # --------------------------------------------------------------------------
 
