@@ -80,6 +80,21 @@ __device__ __forceinline__ void flipw(uint64_t (&x)[W], uint32_t w, uint64_t bit
     }
 }
 
+// LDS accesses through 32-bit LDS addresses (no generic-pointer arithmetic
+// in the search loop)
+template <class T>
+__device__ __forceinline__ T lds_ld(uint32_t a) {
+    return *reinterpret_cast<const __attribute__((address_space(3))) T *>((uintptr_t)a);
+}
+template <class T>
+__device__ __forceinline__ void lds_st(uint32_t a, T v) {
+    *reinterpret_cast<__attribute__((address_space(3))) T *>((uintptr_t)a) = v;
+}
+// LDS address of a __shared__ object
+__device__ __forceinline__ uint32_t lds_of(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
 __device__ __forceinline__ uint32_t d_rw(uint32_t d) { return (d >> 6) & 3u; }
 __device__ __forceinline__ uint32_t d_cw(uint32_t d) { return (d >> 14) & 3u; }
 __device__ __forceinline__ uint32_t d_md(uint32_t d) { return 0u - ((d >> 16) & 1u); }
@@ -93,9 +108,19 @@ struct Lane {
     uint32_t md, ad;    // diagonal masks
     uint32_t cand;      // remaining candidates at the current level
     uint32_t cur;       // descriptor of the current level's cell
-    int d;              // current level
-    int start;          // level at which this task began
-    uint64_t cnt;       // squares completed by this task
+    uint32_t da;        // LDS address of the current level's descriptor (base + 4 * level)
+    uint32_t da0;       // the same for the level at which this task began
+    uint32_t sa;        // LDS address of this lane's stack entry for the current level
+    uint32_t c32;       // squares completed since the last flush()
+    uint64_t cnt;       // squares completed by this task (after flush())
+
+    // levels, given the LDS address of the descriptor table
+    __device__ __forceinline__ int depth(uint32_t dbase) const { return (int)((da - dbase) >> 2); }
+    __device__ __forceinline__ int start_level(uint32_t dbase) const { return (int)((da0 - dbase) >> 2); }
+    __device__ __forceinline__ void flush() {
+        cnt += c32;
+        c32 = 0u;
+    }
 
     __device__ __forceinline__ uint32_t cands(uint32_t desc) const {
         const uint32_t r = (uint32_t)(pickw<G::WR>(R, d_rw(desc)) >> (desc & 63u));
@@ -120,31 +145,38 @@ struct Lane {
         }
     }
 
-    __device__ __forceinline__ bool done() const { return cand == 0u && d == start; }
+    __device__ __forceinline__ bool done() const { return cand == 0u && da == da0; }
 
-    // One DFS step; requires !done().  sdesc: level descriptors (LDS); the
-    // stack entry of level l sits at byte  lane_off + l * stride  of `lds`.
+    // One DFS step; requires !done().  Level descriptors sit 4 bytes apart
+    // and this lane's stack entries `stride` bytes apart in LDS; da and sa
+    // track the current level's entries, so moving one level is an add.
+    // da_last = address of the last level's descriptor.
     template <class S>
-    __device__ __forceinline__ void step(const uint32_t *sdesc, unsigned char *lds, uint32_t lane_off,
-                                         uint32_t stride, int last) {
+    __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last) {
         const bool up = (cand == 0u);
-        const int nd = up ? d - 1 : d + 1;
-        const uint32_t ndesc = sdesc[nd];
-        const uint32_t saved = *reinterpret_cast<const S *>(lds + (lane_off + (uint32_t)(up ? d - 1 : d) * stride));
+        const uint32_t nda = da + (up ? 0u - 4u : 4u);
+        const uint32_t nsa = sa + (up ? 0u - stride : stride);
+        const uint32_t ndesc = lds_ld<uint32_t>(nda);
+        const uint32_t saved = lds_ld<S>(up ? nsa : sa);
         // up lanes write 0 into a slot nobody reads again
-        *reinterpret_cast<S *>(lds + (lane_off + (uint32_t)d * stride)) = (S)cand;
+        lds_st<S>(sa, (S)cand);
         const uint32_t stored = up ? saved : cand;
         const uint32_t b = stored & (0u - stored);
         toggle(up ? ndesc : cur, b);
         const uint32_t nc = cands(ndesc);
-        const bool leaf = (nd == last);
-        cnt += leaf ? (uint64_t)__builtin_popcount(nc) : 0ull;
+        const bool leaf = (nda == da_last);
+        c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
         cand = up ? (stored ^ b) : (leaf ? 0u : nc);
         cur = ndesc;
-        d = nd;
+        da = nda;
+        sa = nsa;
     }
 
-    __device__ __forceinline__ void from_rec(const Rec<N, VS> &r, const uint32_t *sdesc, int last) {
+    // Start the task of record r.  dbase: LDS address of the descriptor
+    // table; lane_off / stride: LDS address of this lane's level-0 stack entry
+    // and the distance between levels.
+    __device__ __forceinline__ void from_rec(const Rec<N, VS> &r, const uint32_t *sdesc, int last,
+                                             uint32_t dbase = 0u, uint32_t lane_off = 0u, uint32_t stride = 0u) {
 #pragma unroll
         for (int k = 0; k < G::WR; ++k) R[k] = r.R[k];
 #pragma unroll
@@ -152,17 +184,20 @@ struct Lane {
         md = r.diag & 0xFFFFu;
         ad = r.diag >> 16;
         cnt = 0;
+        c32 = 0u;
         const uint32_t lvl = r.cl >> 16;
         if (lvl == kNone) {
             cand = 0u;
-            d = start = 0;
+            da = da0 = dbase;
+            sa = lane_off;
             return;
         }
         cand = r.cl & 0xFFFFu;
-        d = start = (int)lvl;
+        da = da0 = dbase + 4u * lvl;
+        sa = lane_off + lvl * stride;
         cur = sdesc[lvl];
         if ((int)lvl == last) {
-            cnt = (uint64_t)__builtin_popcount(cand);
+            c32 = (uint32_t)__builtin_popcount(cand);
             cand = 0u;
         }
     }
@@ -316,14 +351,21 @@ __global__ void __launch_bounds__(1024) plain_kernel(const Plan plan, const Rec<
     if (idx >= num) return;
     const Rec<N, VS> r = recs[idx];
     if ((r.cl >> 16) == kNone) return;  // result already written by the prep kernel
-    Lane<N, VS> L;
-    L.from_rec(r, sdesc, nlev - 1);
-    const uint32_t lane_off = kStackBase + threadIdx.x * (uint32_t)sizeof(S);
+    const uint32_t dbase = lds_of(smem);
+    const uint32_t lane_off = dbase + kStackBase + threadIdx.x * (uint32_t)sizeof(S);
     const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
+    const uint32_t da_last = dbase + 4u * (uint32_t)(nlev - 1);
+    Lane<N, VS> L;
+    L.from_rec(r, sdesc, nlev - 1, dbase, lane_off, stride);
     uint64_t nsteps = 0;
-    while (!L.done()) {
-        L.template step<S>(sdesc, smem, lane_off, stride, nlev - 1);
-        if (STATS) ++nsteps;
+    // the 32-bit step counter is folded into the 64-bit count every 256 steps
+    for (;;) {
+        for (int k = 0; k < 256 && !L.done(); ++k) {
+            L.template step<S>(stride, da_last);
+            if (STATS) ++nsteps;
+        }
+        L.flush();
+        if (L.done()) break;
     }
     counts[idx] = L.cnt;
     if (STATS && steps) atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
@@ -353,9 +395,9 @@ constexpr uint64_t kStallTicks = 100000000ull * 20;
 // keeps only the branch in progress.
 template <int N, bool VS, class SlotOf>
 __device__ __forceinline__ Rec<N, VS> donate(const Lane<N, VS> &L, int lvl, const uint32_t *sdesc, SlotOf slot_of,
-                                             uint32_t origin) {
+                                             uint32_t origin, uint32_t dbase) {
     Lane<N, VS> T = L;
-    for (int l = L.d - 1; l >= lvl; --l) {
+    for (int l = L.depth(dbase) - 1; l >= lvl; --l) {
         const uint32_t sv = *slot_of(l);
         T.toggle(sdesc[l], sv & (0u - sv));
     }
@@ -400,9 +442,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     const int lane = threadIdx.x & 63;
     const bool poller = (threadIdx.x >> 6) == 0;  // one wave per workgroup waits for donations
     const uint64_t below = (1ull << lane) - 1ull;
-    const uint32_t lane_off = kStackBase + threadIdx.x * (uint32_t)sizeof(S);
+    const uint32_t dbase = lds_of(smem);
+    const uint32_t loff = kStackBase + threadIdx.x * (uint32_t)sizeof(S);  // from smem
+    const uint32_t lane_off = dbase + loff;                                   // LDS address
     const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
-    auto slot_of = [&](int l) -> S * { return reinterpret_cast<S *>(smem + (lane_off + (uint32_t)l * stride)); };
+    auto slot_of = [&](int l) -> S * { return reinterpret_cast<S *>(smem + (loff + (uint32_t)l * stride)); };
     const int last = nlev - 1;
     const uint64_t cap = (uint64_t)item_cap;
     // donation across the chip is on only with a positive steal_depth
@@ -418,8 +462,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
 
     Lane<N, VS> L;
     L.cand = 0u;
-    L.d = L.start = 0;
+    L.da = L.da0 = dbase;
+    L.sa = lane_off;
     L.cnt = 0;
+    L.c32 = 0u;
+    const uint32_t da_last = dbase + 4u * (uint32_t)last;
     bool has = false;           // lane holds a task (possibly finished)
     uint64_t *out = &ctrl->sink;  // where this lane's task count goes (a sink until the first task)
     uint64_t stored = 0;        // part of L.cnt already in *out
@@ -436,10 +483,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
         // ---------------- search ----------------
         for (int it = 0; it < tune.refill_every; ++it) {
             if (has && !L.done()) {
-                L.template step<S>(sdesc, smem, lane_off, stride, last);
+                L.template step<S>(stride, da_last);
                 if (STATS) ++nsteps;
             }
         }
+        L.flush();
         const bool fin = has && L.done();
         uint64_t want = __ballot(!has || fin);
 
@@ -489,7 +537,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                 __builtin_amdgcn_s_waitcnt(kWaitVm1);
                 if (fin) has = false;
                 if (my_id >= 0) {
-                    L.from_rec(r, sdesc, last);
+                    L.from_rec(r, sdesc, last, dbase, lane_off, stride);
                     out = &counts[r.origin];
                     stored = 0;
                     has = true;
@@ -514,8 +562,9 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
         if (want && want != ~0ull) {
             int lvl = -1;
             if (has && !L.done()) {
-                const int top = L.d < last - 1 ? L.d : last - 1;
-                for (int l = L.start; l < top; ++l) {
+                const int dep = L.depth(dbase);
+                const int top = dep < last - 1 ? dep : last - 1;
+                for (int l = L.start_level(dbase); l < top; ++l) {
                     const uint32_t sv = *slot_of(l);
                     if (sv & (sv - 1u)) {
                         lvl = l;
@@ -530,14 +579,14 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                 const uint64_t drank = (uint64_t)__popcll(donors & below);
                 const uint64_t rrank = (uint64_t)__popcll(want & below);
                 if (lvl >= 0 && drank < m) {
-                    const Rec<N, VS> r = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts));
+                    const Rec<N, VS> r = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts), dbase);
                     mbox[drank] = r;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 if (!has && rrank < m) {
                     const Rec<N, VS> r = mbox[rrank];
-                    L.from_rec(r, sdesc, last);
+                    L.from_rec(r, sdesc, last, dbase, lane_off, stride);
                     out = &counts[r.origin];
                     stored = 0;
                     has = true;
@@ -615,7 +664,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                         __threadfence();
                         const Rec<N, VS> r = items[slot];
                         __hip_atomic_store(&ready[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        L.from_rec(r, sdesc, last);
+                        L.from_rec(r, sdesc, last, dbase, lane_off, stride);
                         out = &counts[r.origin];
                         stored = 0;
                         has = true;
@@ -662,8 +711,9 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
         if (cap > 0 && lim > 0 && want == 0 && hungry > rsv - hd) {
             int lvl = -1;
             if (!L.done()) {
-                const int top = L.d < lim ? L.d : lim;
-                for (int l = L.start; l < top; ++l) {
+                const int dep = L.depth(dbase);
+                const int top = dep < lim ? dep : lim;
+                for (int l = L.start_level(dbase); l < top; ++l) {
                     const uint32_t sv = *slot_of(l);
                     if (sv & (sv - 1u)) {
                         lvl = l;
@@ -677,7 +727,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
             if (lvl >= 0 && (uint64_t)__popcll(donors & below) < quota) {
                 const uint64_t slot = atomicAdd((unsigned long long *)&ctrl->dq_reserve, 1ull);
                 if (slot < cap) {
-                    items[slot] = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts));
+                    items[slot] = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts), dbase);
                     __threadfence();
                     __hip_atomic_store(&ready[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }

@@ -7,11 +7,13 @@ A request is (order N, flags, prefix); its answer is the exact number of DLS
 * admits a waiting request as soon as one of `slots` execution slots is free
   and its device memory fits the budget (`mem_budget` bytes of prefixes,
   task records and counts in flight);
-* splits the request's prefix on the host into enough workunits to spread it
-  over the GPU (Sec. 5.2) -- a request is one batch of workunits;
-* launches the batch on the slot's own HIP stream (persistent kernel, grid
-  sized to the batch), so requests admitted while others run execute on the
-  device at the same time; the per-request total is reduced on the device;
+* launches the request's prefix on the slot's own HIP stream: the library
+  deepens it on the device (breadth-first passes, the split of Sec. 5.2 done
+  on the GPU) into enough tasks for the slot's share of the chip, then runs
+  the persistent kernel; requests admitted while others run execute on the
+  device at the same time; the per-request total is reduced on the device.
+  (With host_split, the prefix is instead split on the host into at least
+  min_tasks workunits before the launch.)
 * retires a request when its stream's event completes and frees its slot and
   memory for the next one.
 
@@ -50,6 +52,8 @@ class Result:
     admitted: float
     done: float
     tasks: int
+    n: int = 0
+    vs: bool = False
 
     @property
     def latency(self) -> float:
@@ -74,13 +78,15 @@ def _split_target(n: int, flags: int, prefix: np.ndarray, target: int, max_depth
 
 class Server:
     def __init__(self, slots: int = 4, mem_budget: int = 1 << 30, min_tasks: int = 4096,
-                 device: int = 0):
+                 device: int = 0, host_split: bool = False, expand_target: int = 1 << 15):
         import torch
         self.torch = torch
         self.dev = torch.device(f"cuda:{device}")
         self.slots = slots
         self.mem_budget = mem_budget
         self.min_tasks = min_tasks
+        self.host_split = host_split
+        self.expand_target = expand_target
         # default-priority streams, one per execution slot
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
         self.free = list(range(slots))
@@ -98,10 +104,15 @@ class Server:
             d_pre = torch.from_numpy(tasks).to(self.dev, non_blocking=False)
             d_cnt = torch.empty(max(1, len(tasks)), dtype=torch.int64, device=self.dev)
             d_st = torch.zeros(1, dtype=torch.int32, device=self.dev)
-        # grid sized to the batch: one resident workgroup per CU for small
-        # batches so that several requests share the chip, more for big ones
-        bpc = int(min(8, max(1, len(tasks) // (self.cus * 256))))
-        launch = DlsLaunch(block=256, blocks_per_cu=bpc, steal_depth=0, refill_every=0)
+        if self.host_split:
+            # grid sized to the batch: one resident workgroup per CU for small
+            # batches so that several requests share the chip, more for big ones
+            bpc = int(min(8, max(1, len(tasks) // (self.cus * 256))))
+            launch = DlsLaunch(block=256, blocks_per_cu=bpc, steal_depth=0, refill_every=0, expand_target=-1)
+        else:
+            # each slot gets an equal share of the chip's resident workgroups
+            bpc = max(1, 8 // self.slots)
+            launch = DlsLaunch(block=256, blocks_per_cu=bpc, expand_target=self.expand_target)
         pattern = (tasks[0] != EMPTY).astype(np.uint8)
         dls_count_async_ex(req.n, flags, pattern, d_pre, len(tasks), d_cnt, d_st, st, launch)
         with torch.cuda.stream(st):
@@ -131,7 +142,7 @@ class Server:
                         raise RuntimeError(f"request {req.rid}: device status {status}")
                     count = int(job["total"].item()) if ntask else 0
                     results.append(Result(req.rid, count, req.arrival if realtime else 0.0, adm,
-                                          time.perf_counter() - t0, ntask))
+                                          time.perf_counter() - t0, ntask, req.n, req.vs))
                     self.mem_used -= nbytes
                     self.free.append(slot)
                     del running[slot]
@@ -139,7 +150,10 @@ class Server:
             while waiting and self.free:
                 req = waiting[0]
                 flags = DLS_VSYM if req.vs else 0
-                tasks = _split_target(req.n, flags, req.prefix, self.min_tasks)
+                if self.host_split:
+                    tasks = _split_target(req.n, flags, req.prefix, self.min_tasks)
+                else:
+                    tasks = np.ascontiguousarray(req.prefix.reshape(1, -1), dtype=np.uint8)
                 nbytes = self._bytes(req.n, len(tasks))
                 if running and self.mem_used + nbytes > self.mem_budget:
                     break
@@ -147,7 +161,8 @@ class Server:
                 slot = self.free.pop()
                 adm = time.perf_counter() - t0
                 if len(tasks) == 0:
-                    results.append(Result(req.rid, 0, req.arrival if realtime else 0.0, adm, adm, 0))
+                    results.append(Result(req.rid, 0, req.arrival if realtime else 0.0, adm, adm, 0,
+                                          req.n, req.vs))
                     self.free.append(slot)
                     continue
                 job = self._launch(slot, req, tasks)
@@ -161,10 +176,20 @@ class Server:
         return sorted(results, key=lambda r: r.rid)
 
 
-def latency_stats(results: List[Result]) -> dict:
-    lat = np.array([r.latency for r in results])
+def _stats(lat) -> dict:
+    lat = np.asarray(lat)
     return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_ms": float(lat.mean() * 1e3), "n": len(results)}
+            "mean_ms": float(lat.mean() * 1e3), "n": int(len(lat))}
+
+
+def latency_stats(results: List[Result]) -> dict:
+    """p50/p99/mean latency overall and per order N."""
+    out = _stats([r.latency for r in results])
+    per = {}
+    for n in sorted({r.n for r in results}):
+        per[str(n)] = _stats([r.latency for r in results if r.n == n])
+    out["per_order"] = per
+    return out
 
 
 def main(argv=None):
@@ -182,13 +207,15 @@ def main(argv=None):
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--fractions", default="0.25,0.5,0.75,0.9,1.1")
     ap.add_argument("--seed", type=int, default=dls_workloads.DEFAULT_SEED)
+    ap.add_argument("--host-split", action="store_true")
+    ap.add_argument("--expand-target", type=int, default=1 << 15)
     args = ap.parse_args(argv)
 
     def requests(rate, seed):
         jobs = dls_workloads.job_stream(args.jobs, rate, seed=seed)
         return [Request(j.jid, j.n, j.vs, j.prefix, j.arrival) for j in jobs]
 
-    srv = Server(slots=args.slots)
+    srv = Server(slots=args.slots, host_split=args.host_split, expand_target=args.expand_target)
     warm = requests(1.0, args.seed + 1)[:8]
     srv.run(warm, realtime=False)
     reqs = requests(1.0, args.seed)

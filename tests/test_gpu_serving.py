@@ -26,10 +26,11 @@ def _requests(count, seed, k_range=None):
     return [Request(j.jid, j.n, j.vs, j.prefix, j.arrival) for j in jobs]
 
 
-def test_mix_equals_solo_equals_oracle():
+@pytest.mark.parametrize("host_split", [False, True])
+def test_mix_equals_solo_equals_oracle(host_split):
     from paper_1709_02599_amd.serve import Server
     reqs = _requests(40, seed=5)
-    srv = Server(slots=4, min_tasks=2048)
+    srv = Server(slots=4, min_tasks=2048, host_split=host_split)
     mix = srv.run(reqs, realtime=False)
     assert [r.rid for r in mix] == [q.rid for q in reqs]
     for q, r in zip(reqs, mix):
@@ -45,9 +46,12 @@ def test_mix_equals_solo_equals_oracle():
 def test_realtime_arrivals_and_admission_by_memory():
     from paper_1709_02599_amd.serve import Server, latency_stats
     reqs = _requests(16, seed=7)
-    srv = Server(slots=2, mem_budget=1 << 20, min_tasks=1024)   # tight: one request at a time mostly
+    # host-split requests of about 1024 workunits: a 1 MiB budget admits one
+    # at a time mostly
+    srv = Server(slots=2, mem_budget=1 << 20, min_tasks=1024, host_split=True)
     res = srv.run(reqs, realtime=True)
     ref = Server(slots=4).run(reqs, realtime=False)
     assert [a.count for a in res] == [b.count for b in ref]
     st = latency_stats(res)
     assert st["n"] == 16 and st["p99_ms"] >= st["p50_ms"] > 0
+    assert sum(v["n"] for v in st["per_order"].values()) == 16

@@ -195,6 +195,28 @@ def test_canonical_hourglasses_order8_equal_oracle():
     assert np.array_equal(mult[order], omult)
 
 
+def _vs_hourglass_depth(n):
+    o = dls.dls_order(n, dls.DLS_VSYM | dls.DLS_SYMBREAK)
+    hc = set(oracle.hourglass_cells(n))
+    return len([c for c in o if c in hc or (c // n) * n + (n - 1 - c % n) in hc])
+
+
+@pytest.mark.parametrize("n", [6, 8, 10])
+def test_vs_canonical_hourglasses_equal_oracle(n):
+    # vertical symmetry with symmetry breaking (Sec. 5.4): the library's
+    # product-of-tables group against the oracle's generator closure
+    pre, mult = dls.dls_split(n, dls.DLS_VSYM | dls.DLS_SYMBREAK, _vs_hourglass_depth(n))
+    nh, reps, omult = oracle.hourglass_classes(n, vs=True)
+    order = np.lexsort(pre.T[::-1])
+    assert np.array_equal(pre[order], reps)
+    assert np.array_equal(mult[order], omult)
+    assert int(mult.astype(np.int64).sum()) == nh
+    if n == 10:
+        # the vertical mirror acts trivially on VS squares: classes of at
+        # most 2^5 * 4! = 768 (Sec. 5.4)
+        assert int(mult.max()) == 768
+
+
 def test_canon_single_designs_match_oracle():
     rng = np.random.default_rng(11)
     for n in (6, 7, 8):
