@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "order-8 DLS enumerated/sec (exact counts), persistent batched vs plain kernel"
 ORDER8_FIXED = 7447587840            # paper Sec. 5.1
+VS10_FIXED = 82731715264512          # paper Sec. 5.4
 # MI355X integer VALU: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one 32-bit op per lane-cycle
 INT_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
@@ -90,6 +91,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-vs10", action="store_true",
+                    help="skip the full count of vertically symmetric order-10 squares")
     ap.add_argument("--profile-only", action="store_true",
                     help="a few persistent launches only (for rocprofv3 runs)")
     return ap.parse_args()
@@ -269,6 +272,32 @@ def main():
                                "exact": int(s.item()) == ORDER8_FIXED}
         del sd_pre, sd_cnt
 
+    # ---------------- VS order 10, full count with symmetry breaking (Sec. 5.4) ----------------
+    vs10 = None
+    if not args.no_vs10:
+        fl = dls.DLS_VSYM | dls.DLS_SYMBREAK
+        t0 = time.perf_counter()
+        vpre, vmult = dls.dls_split(10, fl, 15)      # 9 508 hourglass classes + 2 cell pairs
+        vsplit = time.perf_counter() - t0
+        vd = torch.from_numpy(vpre).to(dev)
+        vm = torch.from_numpy(vmult.astype(np.int32)).to(dev)
+        vc = torch.zeros(len(vpre), dtype=torch.int64, device=dev)
+        vt = torch.zeros(1, dtype=torch.int64, device=dev)
+        vpat = (vpre[0] != 0xFF).astype(np.uint8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dls.dls_count_async_ex(10, dls.DLS_VSYM, vpat, vd, len(vpre), vc, d_status, stream,
+                               launch_of(dls, {}, time_kernel=1))
+        dls.dls_reduce_weighted(vc, vm, len(vpre), vt, stream)
+        torch.cuda.synchronize()
+        vwall = time.perf_counter() - t0
+        vms, _ = dls.dls_kernel_time_ms(stream)
+        vleaves = int(vc.sum().item())
+        vs10 = {"prefixes": len(vpre), "split_seconds_host": vsplit, "kernel_s": vms * 1e-3,
+                "seconds": vwall, "leaves": vleaves, "leaves_per_s": vleaves / (vms * 1e-3),
+                "total": int(vt.item()), "exact": int(vt.item()) == VS10_FIXED and int(d_status.item()) == 0}
+        del vd, vm, vc
+
     # ---------------- CPU oracle on a bounded sample of the same workload ----------------
     # The oracle builds its own sample: seeded canonical hourglasses (its own
     # classes), each extended by every filling of row 1 along its own order.
@@ -332,6 +361,7 @@ def main():
         "persistent_kernel_ms": p["kernel_ms"],
         "graph": graph,
         "order7_diag_split": order7,
+        "vs_order10_full": vs10,
         "speedup_persistent_vs_plain": results["plain"]["ms_per_step"] / p["ms_per_step"],
         "effective_counted_per_s": weighted / (p["ms_per_step"] * 1e-3),
         "dfs_steps_per_launch": total_steps,
@@ -339,7 +369,7 @@ def main():
         "split_seconds_host": split_s,
         "sustained_full_count": sustained,
         "exact": (all(r["exact"] for r in results.values()) and all(g["exact"] for g in graph.values())
-                  and order7["exact"]),
+                  and order7["exact"] and (vs10 is None or vs10["exact"])),
     }
     print(json.dumps(line))
 

@@ -307,3 +307,54 @@ def test_vs_order10_sampled_prefixes():
     se = total * x.std(ddof=1) / np.sqrt(len(x))
     paper = golden_io.counts()[(10, "vs_fixed")]
     assert abs(est - paper) < 3 * se, (est, paper, se)
+
+
+def _oracle_vs_symbreak_split(n, extra):
+    """The oracle's own workunits: its canonical VS hourglasses, each extended
+    by all fillings of the next `extra` left-half cells of its own order."""
+    hc = oracle.hourglass_cells(n)
+    order = oracle.fill_order(n, first=hc, vs=True)
+    hset = set(hc)
+    hl = len([c for c in order if c in hset or (c // n) * n + (n - 1 - c % n) in hset])
+    cells = []
+    for c in order[hl:hl + extra]:
+        cells.append(c)
+        m = (c // n) * n + (n - 1 - c % n)
+        if m != c:
+            cells.append(m)
+    _, reps, rmult = oracle.hourglass_classes(n, vs=True)
+    rows, mults = [], []
+    for h, m in zip(reps, rmult):
+        ext = oracle.assignments(n, h, cells, vs=True)
+        rows.append(ext)
+        mults.append(np.full(len(ext), m, np.uint32))
+    return hl, np.concatenate(rows), np.concatenate(mults)
+
+
+def test_vs_order8_symmetry_broken_total():
+    n = 8
+    hl, opre, omult = _oracle_vs_symbreak_split(n, 2)
+    pre, mult = dls.dls_split(n, dls.DLS_VSYM | dls.DLS_SYMBREAK, hl + 2)
+    a, b = np.lexsort(pre.T[::-1]), np.lexsort(opre.T[::-1])
+    assert np.array_equal(pre[a], opre[b]) and np.array_equal(mult[a], omult[b])
+    c, st = gpu_counts(dls, n, dls.DLS_VSYM, pre)
+    assert st == 0
+    assert np.array_equal(c[a], oracle.count_many(n, opre[b], vs=True))
+    assert weighted_total(c, mult) == oracle.count(n, oracle.identity_prefix(n), vs=True)
+
+
+def test_vs_order10_full_count_with_symmetry_breaking():
+    # Sec. 5.4: all vertically symmetric DLS of order 10 with the first row
+    # fixed, through the 9 508 canonical VS hourglasses (classes of up to 768)
+    # extended by two more cell pairs: 165 316 workunits, about 1.1e11 squares
+    n = 10
+    hl, opre, omult = _oracle_vs_symbreak_split(n, 2)
+    pre, mult = dls.dls_split(n, dls.DLS_VSYM | dls.DLS_SYMBREAK, hl + 2)
+    a, b = np.lexsort(pre.T[::-1]), np.lexsort(opre.T[::-1])
+    assert np.array_equal(pre[a], opre[b]) and np.array_equal(mult[a], omult[b])
+    c, st = gpu_counts(dls, n, dls.DLS_VSYM, pre)
+    assert st == 0
+    assert weighted_total(c, mult) == golden_io.counts()[(10, "vs_fixed")]
+    # element-wise parity on seeded positions the oracle counts one by one
+    pos = workloads.sample_positions(len(pre), 24, seed=1054)
+    assert np.array_equal(c[a][pos], oracle.count_many(n, opre[b][pos], vs=True))
