@@ -172,6 +172,26 @@ typedef struct {
                            (0 = default 8; at most 65536)                  */
 } dls_launch;
 
+/*
+ * Partial squares on a given cell list (the incomplete squares DLS_N^k of
+ * Sec. 5.3, formed by the first k cells of a fixed order): counts_out[k] =
+ * the number of ways to assign exactly the cells cells[0..ncells) (flat
+ * indices, each empty in every prefix, in this order) so that no row,
+ * column or diagonal repeats a value among assigned cells.  Other empty
+ * cells stay empty.  With DLS_VSYM the cells are left-half cells (column
+ * j <= (n-1)/2) and each assignment also sets its mirror to n-1-v.  ncells =
+ * 0 counts 1 per consistent prefix.  Errors as dls_count; DLS_EINVAL for a
+ * cell out of range, repeated, assigned in a prefix, or (VS) in the right
+ * half.  The _async form takes device buffers, the pattern of assigned cells
+ * shared by all prefixes, and a launch shape, as dls_count_async_ex.
+ */
+int dls_count_cells(int n, uint32_t flags, const int *cells, int ncells,
+                    const uint8_t *prefixes, int64_t num, uint64_t *counts_out);
+int dls_count_cells_async(int n, uint32_t flags, const int *cells, int ncells,
+                          const uint8_t *pattern, const uint8_t *d_prefixes,
+                          int64_t num, uint64_t *d_counts, uint32_t *d_status,
+                          void *stream, const dls_launch *launch);
+
 /* Mean duration in milliseconds of the search kernels launched with
  * time_kernel on `stream` since the previous call (at most 65536 launches),
  * and their number in *launches_out (may be NULL).  Resets the tally.  The

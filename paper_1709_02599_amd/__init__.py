@@ -20,7 +20,8 @@ __all__ = [
     "dls_version", "dls_strerror", "dls_last_hip_error", "dls_order", "dls_split", "dls_split_from",
     "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async",
     "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
-    "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms",
+    "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
+    "dls_count_cells_async",
 ]
 
 DLS_VSYM = 1 << 0
@@ -93,6 +94,11 @@ def _load() -> ctypes.CDLL:
         "dls_reduce_weighted": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
         "dls_kernel_time_ms": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_int64)]),
+        "dls_count_cells": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.c_int, u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]),
+        "dls_count_cells_async": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
+                                                 ctypes.c_int, u8p, vp, ctypes.c_int64, vp, vp, vp,
+                                                 ctypes.POINTER(DlsLaunch)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -288,3 +294,31 @@ def dls_kernel_time_ms(stream=None):
     _check(_lib.dls_kernel_time_ms(_stream(stream), ctypes.byref(ms), ctypes.byref(k)),
            "dls_kernel_time_ms")
     return float(ms.value), int(k.value)
+
+
+def _cells(cells):
+    arr = np.ascontiguousarray(np.asarray(list(cells), dtype=np.int32))
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(arr)
+
+
+def dls_count_cells(n: int, flags: int, cells, prefixes) -> np.ndarray:
+    """Partial squares: for each prefix, the number of consistent assignments
+    of exactly `cells` (Sec. 5.3's incomplete squares)."""
+    keep, cp, nc = _cells(cells)
+    pre = np.ascontiguousarray(np.asarray(prefixes, dtype=np.uint8).reshape(-1, n * n))
+    out = np.zeros(len(pre), dtype=np.uint64)
+    _check(_lib.dls_count_cells(n, flags, cp, nc, _u8(pre), len(pre),
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), "dls_count_cells")
+    del keep
+    return out
+
+
+def dls_count_cells_async(n: int, flags: int, cells, pattern, d_prefixes, num: int, d_counts,
+                          d_status=None, stream=None, launch=None) -> None:
+    keep, cp, nc = _cells(cells)
+    pat = _pattern(n, pattern)
+    lc = _launch(launch)
+    _check(_lib.dls_count_cells_async(n, flags, cp, nc, None if pat is None else _u8(pat), _ptr(d_prefixes),
+                                      num, _ptr(d_counts), _ptr(d_status), _stream(stream),
+                                      None if lc is None else ctypes.byref(lc)), "dls_count_cells_async")
+    del keep

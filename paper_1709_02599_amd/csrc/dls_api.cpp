@@ -218,7 +218,11 @@ int expand_buffers(void *stream, QueueSlot *q, int64_t ecap, size_t rb) {
     return DLS_OK;
 }
 
-int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan, int variant = 0) {
+// cells == nullptr: the levels follow the fill order of Sec. 2.3 (variant);
+// otherwise they are exactly cells[0..ncells) in that order, each empty in
+// the pattern (with vs: left-half cells, the mirror implied).
+int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan, int variant = 0,
+               const int *cells = nullptr, int ncells = 0) {
     std::vector<uint8_t> pat((size_t)n * n, 0);
     if (pattern) {
         for (int c = 0; c < n * n; ++c) pat[c] = pattern[c] ? 1 : 0;
@@ -230,7 +234,21 @@ int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan, int var
             for (int j = 0; j < n; ++j)
                 if (pat[i * n + j] != pat[i * n + (n - 1 - j)]) return DLS_EINVAL;
     if (variant < 0 || variant >= dls::kOrderVariants) return DLS_EINVAL;
-    std::vector<int> order = dls::fill_order(n, vs, pat.data(), {}, variant);
+    std::vector<int> order;
+    if (cells) {
+        if (ncells < 0 || ncells > n * n) return DLS_EINVAL;
+        std::vector<uint8_t> seen(pat);
+        for (int k = 0; k < ncells; ++k) {
+            const int c = cells[k];
+            if (c < 0 || c >= n * n || seen[c]) return DLS_EINVAL;
+            if (vs && 2 * (c % n) > n - 1) return DLS_EINVAL;
+            seen[c] = 1;
+            if (vs) seen[(c / n) * n + (n - 1 - c % n)] = 1;
+            order.push_back(c);
+        }
+    } else {
+        order = dls::fill_order(n, vs, pat.data(), {}, variant);
+    }
     if ((int)order.size() > dlsk::kMaxLevels) return DLS_EINVAL;
     std::memset(&plan, 0, sizeof(plan));
     plan.nlev = (int)order.size();
@@ -242,25 +260,27 @@ int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan, int var
 
 int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,
                      uint64_t *d_counts, uint32_t *d_status, void *stream, const dls_launch *launch,
-                     uint64_t *d_steps) {
+                     uint64_t *d_steps, const int *cells = nullptr, int ncells = 0) {
     if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
     if (num > 0 && (!d_prefixes || !d_counts)) return DLS_EINVAL;
     if (num == 0) return DLS_OK;
     const bool vs = flags & DLS_VSYM;
     hipStream_t st = (hipStream_t)stream;
+    dlsk::LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int rc = (vs && n % 2 == 1 && n > 1) ? DLS_OK
+                                          : build_plan(n, vs, pattern, a.plan, launch ? launch->order_variant : 0,
+                                                       cells, ncells);
+    if (rc) return rc;
     DeviceState *ds = nullptr;
     int dev = 0;
-    int rc = device_state(&ds, &dev);
+    rc = device_state(&ds, &dev);
     if (rc) return rc;
     if (vs && n % 2 == 1 && n > 1) {
         // no vertically symmetric square of odd order > 1 exists
         hipError_t ez = dlsk::launch_zero(d_counts, num, st);
         return ez == hipSuccess ? DLS_OK : hip_fail(ez, DLS_EDEVICE);
     }
-    dlsk::LaunchArgs a;
-    std::memset(&a, 0, sizeof(a));
-    rc = build_plan(n, vs, pattern, a.plan, launch ? launch->order_variant : 0);
-    if (rc) return rc;
     a.n = n;
     a.vs = vs;
     a.persistent = !(flags & DLS_PLAIN);
@@ -350,6 +370,71 @@ struct DevBuf {
         if (p) (void)hipFree(p);
     }
 };
+
+
+int count_host(int n, uint32_t flags, const uint8_t *prefixes, int64_t num, uint64_t *counts_out, const int *cells,
+               int ncells) {
+    if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
+    if (num > 0 && (!prefixes || !counts_out)) return DLS_EINVAL;
+    const int nn = n * n;
+    for (int64_t k = 0; k < num; ++k)
+        if (!valid_cells(n, prefixes + k * nn)) return DLS_EINVAL;
+    if (num == 0) return DLS_OK;
+    const bool vs = flags & DLS_VSYM;
+    std::fill(counts_out, counts_out + num, 0);
+    if (vs && n % 2 == 1 && n > 1) return DLS_OK;
+    try {
+        // group prefixes by which cells they assign (mirror-completed with VS)
+        std::map<std::vector<uint8_t>, std::vector<int64_t>> groups;
+        std::vector<uint8_t> work((size_t)num * nn);
+        for (int64_t k = 0; k < num; ++k) {
+            uint8_t *dst = work.data() + k * nn;
+            if (vs) {
+                if (!dls::vs_complete(n, prefixes + k * nn, dst)) continue;  // count stays 0
+            } else {
+                std::memcpy(dst, prefixes + k * nn, nn);
+            }
+            groups[pattern_of(n, dst)].push_back(k);
+        }
+        if (cells) {
+            // reject a bad cell list before touching the device
+            dlsk::Plan probe;
+            for (auto &g : groups) {
+                int rc0 = build_plan(n, vs, g.first.data(), probe, 0, cells, ncells);
+                if (rc0) return rc0;
+            }
+        }
+        hipStream_t st = nullptr;
+        for (auto &g : groups) {
+            const std::vector<int64_t> &ids = g.second;
+            const int64_t m = (int64_t)ids.size();
+            std::vector<uint8_t> packed((size_t)m * nn);
+            for (int64_t t = 0; t < m; ++t) std::memcpy(packed.data() + t * nn, work.data() + ids[t] * nn, nn);
+            DevBuf dp, dc, dsb;
+            if (hipMalloc(&dp.p, packed.size()) != hipSuccess) return DLS_ENOMEM;
+            if (hipMalloc(&dc.p, sizeof(uint64_t) * m) != hipSuccess) return DLS_ENOMEM;
+            if (hipMalloc(&dsb.p, sizeof(uint32_t)) != hipSuccess) return DLS_ENOMEM;
+            if (hipMemcpy(dp.p, packed.data(), packed.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemset(dsb.p, 0, sizeof(uint32_t)) != hipSuccess)
+                return DLS_EDEVICE;
+            int rc = count_async_impl(n, flags, g.first.data(), (const uint8_t *)dp.p, m, (uint64_t *)dc.p,
+                                      (uint32_t *)dsb.p, st, nullptr, nullptr, cells, ncells);
+            if (rc) return rc;
+            std::vector<uint64_t> c((size_t)m);
+            uint32_t status = 0;
+            if (hipStreamSynchronize(st) != hipSuccess ||
+                hipMemcpy(c.data(), dc.p, sizeof(uint64_t) * m, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(&status, dsb.p, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+                return DLS_EDEVICE;
+            if (status & ~1u) return DLS_EDEVICE;
+            if (status & 1u) return DLS_EPATTERN;
+            for (int64_t t = 0; t < m; ++t) counts_out[ids[t]] = c[t];
+        }
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
 
 }  // namespace
 
@@ -501,59 +586,25 @@ int dls_count_async_stats(int n, uint32_t flags, const uint8_t *pattern, const u
     return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, launch, d_steps);
 }
 
+
 int dls_count(int n, uint32_t flags, const uint8_t *prefixes, int64_t num, uint64_t *counts_out) {
-    if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
-    if (num > 0 && (!prefixes || !counts_out)) return DLS_EINVAL;
-    const int nn = n * n;
-    for (int64_t k = 0; k < num; ++k)
-        if (!valid_cells(n, prefixes + k * nn)) return DLS_EINVAL;
-    if (num == 0) return DLS_OK;
-    const bool vs = flags & DLS_VSYM;
-    std::fill(counts_out, counts_out + num, 0);
-    if (vs && n % 2 == 1 && n > 1) return DLS_OK;
-    try {
-        // group prefixes by which cells they assign (mirror-completed with VS)
-        std::map<std::vector<uint8_t>, std::vector<int64_t>> groups;
-        std::vector<uint8_t> work((size_t)num * nn);
-        for (int64_t k = 0; k < num; ++k) {
-            uint8_t *dst = work.data() + k * nn;
-            if (vs) {
-                if (!dls::vs_complete(n, prefixes + k * nn, dst)) continue;  // count stays 0
-            } else {
-                std::memcpy(dst, prefixes + k * nn, nn);
-            }
-            groups[pattern_of(n, dst)].push_back(k);
-        }
-        hipStream_t st = nullptr;
-        for (auto &g : groups) {
-            const std::vector<int64_t> &ids = g.second;
-            const int64_t m = (int64_t)ids.size();
-            std::vector<uint8_t> packed((size_t)m * nn);
-            for (int64_t t = 0; t < m; ++t) std::memcpy(packed.data() + t * nn, work.data() + ids[t] * nn, nn);
-            DevBuf dp, dc, dsb;
-            if (hipMalloc(&dp.p, packed.size()) != hipSuccess) return DLS_ENOMEM;
-            if (hipMalloc(&dc.p, sizeof(uint64_t) * m) != hipSuccess) return DLS_ENOMEM;
-            if (hipMalloc(&dsb.p, sizeof(uint32_t)) != hipSuccess) return DLS_ENOMEM;
-            if (hipMemcpy(dp.p, packed.data(), packed.size(), hipMemcpyHostToDevice) != hipSuccess ||
-                hipMemset(dsb.p, 0, sizeof(uint32_t)) != hipSuccess)
-                return DLS_EDEVICE;
-            int rc = count_async_impl(n, flags, g.first.data(), (const uint8_t *)dp.p, m, (uint64_t *)dc.p,
-                                      (uint32_t *)dsb.p, st, nullptr, nullptr);
-            if (rc) return rc;
-            std::vector<uint64_t> c((size_t)m);
-            uint32_t status = 0;
-            if (hipStreamSynchronize(st) != hipSuccess ||
-                hipMemcpy(c.data(), dc.p, sizeof(uint64_t) * m, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(&status, dsb.p, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
-                return DLS_EDEVICE;
-            if (status & 2u) return DLS_EDEVICE;
-            if (status & 1u) return DLS_EPATTERN;
-            for (int64_t t = 0; t < m; ++t) counts_out[ids[t]] = c[t];
-        }
-    } catch (const std::bad_alloc &) {
-        return DLS_ENOMEM;
-    }
-    return DLS_OK;
+    return count_host(n, flags, prefixes, num, counts_out, nullptr, 0);
+}
+
+int dls_count_cells(int n, uint32_t flags, const int *cells, int ncells, const uint8_t *prefixes, int64_t num,
+                    uint64_t *counts_out) {
+    if (!cells && ncells) return DLS_EINVAL;
+    static const int none = 0;
+    return count_host(n, flags, prefixes, num, counts_out, cells ? cells : &none, ncells);
+}
+
+int dls_count_cells_async(int n, uint32_t flags, const int *cells, int ncells, const uint8_t *pattern,
+                          const uint8_t *d_prefixes, int64_t num, uint64_t *d_counts, uint32_t *d_status,
+                          void *stream, const dls_launch *launch) {
+    if (!cells && ncells) return DLS_EINVAL;
+    static const int none = 0;
+    return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, launch, nullptr,
+                            cells ? cells : &none, ncells);
 }
 
 int dls_kernel_time_ms(void *stream, float *ms_out, int64_t *launches_out) {

@@ -287,3 +287,16 @@ def test_single_hip_runtime_in_process():
     with open("/proc/self/maps") as f:
         libs = {line.split()[-1] for line in f if "libamdhip64" in line}
     assert len(libs) <= 1, libs
+
+
+def test_cell_list_errors_before_the_device():
+    # a bad cell list is rejected without touching the GPU
+    n = 6
+    base = oracle.identity_prefix(n)[None]
+    for cells, flags in (([0], 0),            # assigned in the prefix
+                         ([7, 7], 0),         # repeated
+                         ([n * n], 0),        # out of range
+                         ([n + n - 1], 1)):   # right half with vertical symmetry
+        with pytest.raises(dls.DLSError) as ei:
+            dls.dls_count_cells(n, flags, cells, base)
+        assert ei.value.code == -1, cells

@@ -279,3 +279,26 @@ def test_vs_symmetry_broken_total(n):
     c = oracle.count_many(n, reps, vs=True)
     assert int((c.astype(object) * mult.astype(object)).sum()) == \
         oracle.count(n, oracle.identity_prefix(n), vs=True)
+
+
+def test_count_assignments_brute_force_rows():
+    # partial squares (Sec. 5.3): the oracle's count of consistent assignments
+    # of rows 1-2 of order 5 against brute force over row permutations
+    import itertools
+    n = 5
+    base = oracle.identity_prefix(n)
+    perms = list(itertools.permutations(range(n)))
+
+    def ok(rows):
+        for j in range(n):
+            if len({r[j] for r in rows}) < len(rows):
+                return False
+        md = [rows[i][i] for i in range(len(rows))]
+        ad = [rows[i][n - 1 - i] for i in range(len(rows))]
+        return len(set(md)) == len(md) and len(set(ad)) == len(ad)
+
+    r0 = tuple(range(n))
+    one = sum(1 for p in perms if ok([r0, p]))
+    two = sum(1 for p in perms for q in perms if ok([r0, p, q]))
+    assert oracle.count_assignments(n, base, list(range(n, 2 * n))) == one
+    assert oracle.count_assignments(n, base, list(range(n, 3 * n))) == two
