@@ -116,6 +116,13 @@ int dls_split(int n, uint32_t flags, int depth, uint8_t *prefixes_out, uint32_t 
 int dls_split_from(int n, uint32_t flags, const uint8_t *base, int depth,
                    uint8_t *prefixes_out, int64_t cap, int64_t *num_out);
 
+/* Workunits on a given cell list: every consistent assignment of exactly
+ * cells[0..ncells) (flat indices, empty in base, no repeats; with DLS_VSYM
+ * left-half cells, mirrors implied) on top of base, in depth-first order with
+ * values increasing.  Two-call pattern and errors as dls_split_from. */
+int dls_split_cells(int n, uint32_t flags, const uint8_t *base, const int *cells, int ncells,
+                    uint8_t *prefixes_out, int64_t cap, int64_t *num_out);
+
 /* Uniform sampling of workunits (Sec. 5.3 estimates from a random sample):
  * the prefixes that dls_split(n, flags, depth) would emit at the positions
  * listed in `indices` (k strictly increasing 0-based positions) are written to

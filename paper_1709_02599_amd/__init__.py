@@ -21,7 +21,7 @@ __all__ = [
     "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async",
     "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
-    "dls_count_cells_async",
+    "dls_count_cells_async", "dls_split_cells",
 ]
 
 DLS_VSYM = 1 << 0
@@ -94,6 +94,8 @@ def _load() -> ctypes.CDLL:
         "dls_reduce_weighted": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
         "dls_kernel_time_ms": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float),
                                               ctypes.POINTER(ctypes.c_int64)]),
+        "dls_split_cells": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.c_int, u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
         "dls_count_cells": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
                                            ctypes.c_int, u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]),
         "dls_count_cells_async": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
@@ -322,3 +324,18 @@ def dls_count_cells_async(n: int, flags: int, cells, pattern, d_prefixes, num: i
                                       num, _ptr(d_counts), _ptr(d_status), _stream(stream),
                                       None if lc is None else ctypes.byref(lc)), "dls_count_cells_async")
     del keep
+
+
+def dls_split_cells(n: int, flags: int, base, cells) -> np.ndarray:
+    """Every consistent assignment of exactly `cells` on top of `base`
+    ([P, n*n] uint8, depth-first order)."""
+    keep, cp, nc = _cells(cells)
+    b = _square(n, base)
+    num = ctypes.c_int64(0)
+    _check(_lib.dls_split_cells(n, flags, _u8(b), cp, nc, None, 0, ctypes.byref(num)), "dls_split_cells")
+    out = np.zeros((num.value, n * n), dtype=np.uint8)
+    if num.value:
+        _check(_lib.dls_split_cells(n, flags, _u8(b), cp, nc, _u8(out), num.value, ctypes.byref(num)),
+               "dls_split_cells")
+    del keep
+    return out

@@ -524,6 +524,44 @@ int dls_split_from(int n, uint32_t flags, const uint8_t *base, int depth, uint8_
     return DLS_OK;
 }
 
+int dls_split_cells(int n, uint32_t flags, const uint8_t *base, const int *cells, int ncells,
+                    uint8_t *prefixes_out, int64_t cap, int64_t *num_out) {
+    if (!valid_n(n) || !base || !num_out || ncells < 0 || (ncells > 0 && !cells)) return DLS_EINVAL;
+    if (flags & ~(uint32_t)DLS_VSYM) return DLS_EINVAL;
+    if (!valid_cells(n, base)) return DLS_EINVAL;
+    const bool vs = flags & DLS_VSYM;
+    try {
+        std::vector<uint8_t> b(base, base + n * n);
+        if (vs && !dls::vs_complete(n, base, b.data())) {
+            *num_out = 0;
+            return DLS_OK;
+        }
+        std::vector<uint8_t> seen((size_t)n * n, 0);
+        for (int c = 0; c < n * n; ++c) seen[c] = b[c] != dls::kEmpty;
+        dls::SplitSpec spec;
+        spec.n = n;
+        spec.vs = vs;
+        for (int k = 0; k < ncells; ++k) {
+            const int c = cells[k];
+            if (c < 0 || c >= n * n || seen[c]) return DLS_EINVAL;
+            if (vs && 2 * (c % n) > n - 1) return DLS_EINVAL;
+            seen[c] = 1;
+            if (vs) seen[(c / n) * n + (n - 1 - c % n)] = 1;
+            spec.cells.push_back(c);
+        }
+        if (!prefixes_out) {
+            *num_out = dls::split_count(spec, b.data());
+            return DLS_OK;
+        }
+        int64_t total = dls::split_write(spec, b.data(), prefixes_out, nullptr, cap);
+        *num_out = total;
+        if (total > cap) return DLS_ERANGE;
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
 int dls_split_sample(int n, uint32_t flags, int depth, const int64_t *indices, int64_t k,
                      uint8_t *prefixes_out, int64_t *total_out) {
     if (!valid_n(n) || !total_out || k < 0 || (k > 0 && (!indices || !prefixes_out))) return DLS_EINVAL;

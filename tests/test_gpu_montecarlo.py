@@ -1,0 +1,50 @@
+"""Monte Carlo estimate of Sec. 5.3: the sampler draws incomplete squares
+exactly uniformly, and the estimate of T_fixed is unbiased (checked against
+the oracle on orders where the exact count is cheap)."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+from tests.needs_lib import load as _load_dls  # noqa: E402
+dls = _load_dls()
+import dls_workloads as workloads  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_sampler_is_uniform():
+    from paper_1709_02599_amd.montecarlo import Sampler
+    n, k = 6, 14
+    s = Sampler(n, k, stages=[list(range(6, 10)), [10, 11], [12, 13]])
+    base = oracle.identity_prefix(n)
+    every = oracle.assignments(n, base, list(range(6, 14)))
+    assert s.total == len(every) == oracle.count_assignments(n, base, list(range(6, 14)))
+    index = {bytes(r): i for i, r in enumerate(every)}
+    rng = workloads.SplitMix64(2024)
+    draws = 25 * len(every)
+    hits = np.zeros(len(every), dtype=np.int64)
+    for _ in range(draws):
+        hits[index[bytes(s.draw(rng))]] += 1
+    # chi-square against the uniform law (df = M-1): mean M-1, sd sqrt(2(M-1))
+    m = len(every)
+    chi2 = float(((hits - draws / m) ** 2 / (draws / m)).sum())
+    assert abs(chi2 - (m - 1)) < 5 * np.sqrt(2 * (m - 1)), (chi2, m)
+    assert hits.min() > 0
+
+
+def test_estimate_of_order7_is_unbiased():
+    from paper_1709_02599_amd.montecarlo import estimate
+    n, k = 7, 14
+    r = estimate(n, k, 300, workloads.SplitMix64(77))
+    exact = oracle.count(n, oracle.identity_prefix(n))
+    assert abs(r["estimate"] - exact) < 4 * r["std_error"], r
+    # the per-sample completion counts are exact counts of the drawn squares
+    assert r["squares_counted"] == sum(r["completions"])
