@@ -123,6 +123,15 @@ int dls_split_from(int n, uint32_t flags, const uint8_t *base, int depth,
 int dls_split_cells(int n, uint32_t flags, const uint8_t *base, const int *cells, int ncells,
                     uint8_t *prefixes_out, int64_t cap, int64_t *num_out);
 
+/* Cost of a fill order (Sec. 2.3: the order decides the speed, never the
+ * count): over the host prefixes [num][n*n], the number of downward DFS
+ * steps the search kernels take when they fill exactly cells[0..ncells) in
+ * that order (*steps_out), and the number of squares reached (*leaves_out).
+ * Host only, multithreaded.  DLS_EINVAL for a bad cell list or a cell
+ * assigned in some prefix. */
+int dls_order_cost(int n, uint32_t flags, const int *cells, int ncells, const uint8_t *prefixes,
+                   int64_t num, uint64_t *steps_out, uint64_t *leaves_out);
+
 /* Uniform sampling of workunits (Sec. 5.3 estimates from a random sample):
  * the prefixes that dls_split(n, flags, depth) would emit at the positions
  * listed in `indices` (k strictly increasing 0-based positions) are written to

@@ -21,7 +21,7 @@ __all__ = [
     "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async",
     "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
-    "dls_count_cells_async", "dls_split_cells",
+    "dls_count_cells_async", "dls_split_cells", "dls_order_cost",
 ]
 
 DLS_VSYM = 1 << 0
@@ -96,6 +96,9 @@ def _load() -> ctypes.CDLL:
                                               ctypes.POINTER(ctypes.c_int64)]),
         "dls_split_cells": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.POINTER(ctypes.c_int),
                                            ctypes.c_int, u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+        "dls_order_cost": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                          u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
         "dls_count_cells": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
                                            ctypes.c_int, u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]),
         "dls_count_cells_async": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
@@ -339,3 +342,15 @@ def dls_split_cells(n: int, flags: int, base, cells) -> np.ndarray:
                "dls_split_cells")
     del keep
     return out
+
+
+def dls_order_cost(n: int, flags: int, cells, prefixes):
+    """(DFS steps, squares) of filling `cells` in this order over the host
+    prefixes."""
+    keep, cp, nc = _cells(cells)
+    pre = np.ascontiguousarray(np.asarray(prefixes, dtype=np.uint8).reshape(-1, n * n))
+    st, lv = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(_lib.dls_order_cost(n, flags, cp, nc, _u8(pre), len(pre), ctypes.byref(st), ctypes.byref(lv)),
+           "dls_order_cost")
+    del keep
+    return int(st.value), int(lv.value)

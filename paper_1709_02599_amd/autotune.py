@@ -97,7 +97,7 @@ def time_launch(n: int, flags: int, pattern, d_pre, num: int, d_cnt, d_st, strea
 
 
 def tune(n: int, flags: int, prefixes: np.ndarray, workload: str, space: Optional[Dict[str, Iterable]] = None,
-         default: Optional[dict] = None, reps: int = 3, save: bool = True) -> dict:
+         default: Optional[dict] = None, reps: int = 3, save: bool = True, verbose: bool = True) -> dict:
     """Time every combination of the launch settings in `space` (field ->
     candidate values); all must give identical counts.  Keeps the fastest."""
     import torch
@@ -124,6 +124,8 @@ def tune(n: int, flags: int, prefixes: np.ndarray, workload: str, space: Optiona
         elif digest != ref:
             raise RuntimeError(f"counts differ for {settings}")
         table.append({**settings, "ms": ms})
+        if verbose:
+            print(f"  {settings}: {ms:.3f} ms", flush=True)
     # the plain kernel under the paper's order, for reference
     plain_ms, digest, _ = time_launch(n, flags | DLS_PLAIN, pattern, d_pre, num, d_cnt, d_st, stream,
                                       {"block": 256}, reps)

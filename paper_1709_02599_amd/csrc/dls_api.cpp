@@ -562,6 +562,29 @@ int dls_split_cells(int n, uint32_t flags, const uint8_t *base, const int *cells
     return DLS_OK;
 }
 
+int dls_order_cost(int n, uint32_t flags, const int *cells, int ncells, const uint8_t *prefixes, int64_t num,
+                   uint64_t *steps_out, uint64_t *leaves_out) {
+    if (!valid_n(n) || ncells < 0 || (ncells > 0 && !cells) || num < 0 || (num > 0 && !prefixes)) return DLS_EINVAL;
+    if (!steps_out || !leaves_out || (flags & ~(uint32_t)DLS_VSYM)) return DLS_EINVAL;
+    const bool vs = flags & DLS_VSYM;
+    for (int k = 0; k < ncells; ++k) {
+        const int c = cells[k];
+        if (c < 0 || c >= n * n) return DLS_EINVAL;
+        if (vs && 2 * (c % n) > n - 1) return DLS_EINVAL;
+        for (int t = 0; t < k; ++t)
+            if (cells[t] == c) return DLS_EINVAL;
+    }
+    for (int64_t k = 0; k < num; ++k)
+        if (!valid_cells(n, prefixes + k * n * n)) return DLS_EINVAL;
+    try {
+        std::vector<int> order(cells, cells + ncells);
+        if (dls::order_cost(n, vs, order, prefixes, num, steps_out, leaves_out)) return DLS_EINVAL;
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
 int dls_split_sample(int n, uint32_t flags, int depth, const int64_t *indices, int64_t k,
                      uint8_t *prefixes_out, int64_t *total_out) {
     if (!valid_n(n) || !total_out || k < 0 || (k > 0 && (!indices || !prefixes_out))) return DLS_EINVAL;

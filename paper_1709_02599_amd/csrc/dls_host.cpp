@@ -470,3 +470,107 @@ int64_t split_select(const SplitSpec &s, const uint8_t *base, const int64_t *idx
 }
 
 }  // namespace dls
+
+// ---------------------------------------------------------------------------
+// cost of a fill order: the DFS steps the search kernels would take
+// ---------------------------------------------------------------------------
+
+namespace dls {
+
+namespace {
+
+struct CostLevel {
+    int i, j;
+    uint32_t md, ad;  // all-ones if the cell lies on the diagonal
+};
+
+struct CostState {
+    int n;
+    bool vs;
+    uint32_t rows[kMaxN], cols[kMaxN], md, ad;
+};
+
+// Entries into levels 1..last below level `lvl` (each entry is one downward
+// step of the kernels' search); leaves counted at the last level.
+void cost_dfs(CostState &s, const std::vector<CostLevel> &lv, int lvl, uint64_t &steps, uint64_t &leaves) {
+    const CostLevel &c = lv[lvl];
+    const uint32_t all = (1u << s.n) - 1u;
+    const uint32_t cand = all & ~(s.rows[c.i] | s.cols[c.j] | (s.md & c.md) | (s.ad & c.ad));
+    if (lvl + 1 == (int)lv.size()) {
+        leaves += (uint64_t)__builtin_popcount(cand);
+        return;
+    }
+    for (uint32_t l = cand; l; l &= l - 1u) {
+        const uint32_t b = l & (0u - l);
+        const int v = __builtin_ctz(b);
+        const uint32_t rb = s.vs ? (1u << (s.n - 1 - v)) : 0u;
+        s.rows[c.i] ^= b | rb;
+        s.cols[c.j] ^= b;
+        const uint32_t dm = (b & c.md) | (rb & c.ad), da = (b & c.ad) | (rb & c.md);
+        s.md ^= dm;
+        s.ad ^= da;
+        ++steps;
+        cost_dfs(s, lv, lvl + 1, steps, leaves);
+        s.rows[c.i] ^= b | rb;
+        s.cols[c.j] ^= b;
+        s.md ^= dm;
+        s.ad ^= da;
+    }
+}
+
+}  // namespace
+
+int order_cost(int n, bool vs, const std::vector<int> &order, const uint8_t *prefixes, int64_t num,
+               uint64_t *steps_out, uint64_t *leaves_out) {
+    const int nn = n * n;
+    std::vector<CostLevel> lv;
+    for (int c : order) {
+        const int i = c / n, j = c % n;
+        lv.push_back({i, j, i == j ? ~0u : 0u, i + j == n - 1 ? ~0u : 0u});
+    }
+    std::atomic<int64_t> next(0);
+    std::atomic<uint64_t> steps(0), leaves(0);
+    std::atomic<int> bad(0);
+    auto work = [&]() {
+        uint64_t st = 0, le = 0;
+        for (;;) {
+            const int64_t k = next.fetch_add(1);
+            if (k >= num) break;
+            const uint8_t *p = prefixes + k * nn;
+            std::vector<uint8_t> full(p, p + nn);
+            if (vs && !vs_complete(n, p, full.data())) continue;
+            Board b;
+            b.reset(n);
+            if (!b.load(full.data(), vs)) continue;  // inconsistent prefix: no work
+            for (int c : order)
+                if (b.cell[c] != kEmpty) bad = 1;
+            if (lv.empty()) {
+                ++le;
+                continue;
+            }
+            CostState s;
+            s.n = n;
+            s.vs = vs;
+            for (int t = 0; t < n; ++t) {
+                s.rows[t] = b.rows[t];
+                s.cols[t] = b.cols[t];
+            }
+            s.md = b.md;
+            s.ad = b.ad;
+            cost_dfs(s, lv, 0, st, le);
+        }
+        steps += st;
+        leaves += le;
+    };
+    const int th = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, num));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < th; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    if (bad) return -1;
+    *steps_out = steps;
+    *leaves_out = leaves;
+    return 0;
+}
+
+}  // namespace dls

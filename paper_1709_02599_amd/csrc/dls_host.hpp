@@ -92,4 +92,12 @@ int64_t split_select(const SplitSpec &spec, const uint8_t *base, const int64_t *
 
 int host_threads();
 
+// Cost of a fill order: the number of downward DFS steps (entries into
+// levels below the first) that the search kernels take over the given
+// prefixes when they fill `order` (with vs: left-half cells) in that order,
+// and the number of squares reached.  -1 if an order cell is assigned in a
+// prefix.  Multithreaded over prefixes.
+int order_cost(int n, bool vs, const std::vector<int> &order, const uint8_t *prefixes, int64_t num,
+               uint64_t *steps_out, uint64_t *leaves_out);
+
 }  // namespace dls

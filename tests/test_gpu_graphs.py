@@ -148,3 +148,16 @@ def test_reduce_weighted_matches_host():
         want = int((c.astype(object) * m.astype(object)).sum()) % (1 << 64)
         assert int(out.item()) % (1 << 64) == want, num
         assert int(out1.item()) == int(c.astype(object).sum()), num
+
+
+def test_host_order_cost_equals_device_step_count(order7):
+    # the kernels' instrumented DFS step count (down + up) is twice the host
+    # cost of the same fill order (expansion off: its levels are not steps)
+    pre, _ = order7
+    pattern = (pre[0] != E).astype(np.uint8)
+    for v in (0, 5):
+        _, st, steps = gpu_counts(dls, 7, 0, pre, launch={"order_variant": v, "expand_target": -1},
+                                  steps=True)
+        order = dls.dls_order_variant(7, 0, pattern, v)
+        host_steps, _ = dls.dls_order_cost(7, 0, order, pre)
+        assert st == 0 and steps == 2 * host_steps, v

@@ -300,3 +300,62 @@ def test_cell_list_errors_before_the_device():
         with pytest.raises(dls.DLSError) as ei:
             dls.dls_count_cells(n, flags, cells, base)
         assert ei.value.code == -1, cells
+
+
+def _python_cost(n, prefix, order):
+    """Entries into levels below the first and squares reached, by plain
+    recursion over sets (independent of the library's bitmask code)."""
+    sq = [None if v == 0xFF else int(v) for v in prefix]
+
+    def ok(c, v):
+        i, j = divmod(c, n)
+        for t in range(n):
+            if sq[i * n + t] == v or sq[t * n + j] == v:
+                return False
+        if i == j and any(sq[t * n + t] == v for t in range(n)):
+            return False
+        if i + j == n - 1 and any(sq[t * n + n - 1 - t] == v for t in range(n)):
+            return False
+        return True
+
+    steps = leaves = 0
+
+    def rec(k):
+        nonlocal steps, leaves
+        c = order[k]
+        vals = [v for v in range(n) if ok(c, v)]
+        if k + 1 == len(order):
+            leaves += len(vals)
+            return
+        for v in vals:
+            sq[c] = v
+            steps += 1
+            rec(k + 1)
+            sq[c] = None
+
+    rec(0)
+    return steps, leaves
+
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_order_cost_matches_plain_recursion(n):
+    base = oracle.identity_prefix(n)
+    rng = workloads.SplitMix64(40 + n)
+    empty = list(range(n, n * n))
+    for trial in range(3):
+        order = empty[:]
+        for t in range(len(order) - 1, 0, -1):          # Fisher-Yates with the seeded stream
+            u = rng.below(t + 1)
+            order[t], order[u] = order[u], order[t]
+        cut = order[: {4: len(order), 5: 12, 6: 10}[n]]
+        steps, leaves = dls.dls_order_cost(n, 0, cut, base[None])
+        assert (steps, leaves) == _python_cost(n, base, cut), (n, trial)
+    # a full order reaches every square, whatever the order
+    st, lv = dls.dls_order_cost(n, 0, dls.dls_order(n), base[None])
+    assert lv == oracle.count(n, base)
+
+
+def test_order_cost_rejects_assigned_cells():
+    base = oracle.identity_prefix(6)
+    with pytest.raises(dls.DLSError):
+        dls.dls_order_cost(6, 0, [0, 7], base[None])
