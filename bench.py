@@ -200,6 +200,21 @@ def main():
         ok = int(d_total.item()) == ORDER8_FIXED and int(d_status.item()) == 0
         results[name] = {"ms_per_step": 1e3 * wall / args.steps, "kernel_ms": kernel_ms, "exact": ok}
 
+    # ---------------- measured integer VALU peak ----------------
+    # 8 independent chains of xor / add / rotate per lane: 24 VALU
+    # instructions per iteration, all 2048 lanes per CU resident
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    pblocks, piters = cus * 8, 20000
+    sink = torch.zeros(pblocks * 256, dtype=torch.int32, device=dev)
+    dls.dls_valu_probe(pblocks, 100, sink, stream)
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ea.record(stream)
+    dls.dls_valu_probe(pblocks, piters, sink, stream)
+    eb.record(stream)
+    torch.cuda.synchronize()
+    measured_peak = pblocks * 256 * piters * 24 / (ea.elapsed_time(eb) * 1e-3)
+    del sink
+
     # ---------------- the same step captured in a HIP graph ----------------
     from paper_1709_02599_amd.graphs import CountStep
     graph = {}
@@ -272,6 +287,24 @@ def main():
                                "exact": int(s.item()) == ORDER8_FIXED}
         del sd_pre, sd_cnt
 
+    # ---------------- order 6, one prefix: latency of a single small count ----------------
+    p6 = np.full(36, 0xFF, dtype=np.uint8)
+    p6[:6] = np.arange(6, dtype=np.uint8)
+    d6 = torch.from_numpy(p6[None].copy()).to(dev)
+    c6 = torch.zeros(1, dtype=torch.int64, device=dev)
+    step6 = CountStep(6, 0, (p6 != 0xFF).astype(np.uint8), d6, 1, c6, d_status).capture()
+    order6 = {}
+    for name, fn in (("eager", step6.eager), ("graph", step6.replay)):
+        fn()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(200):
+            fn()
+        torch.cuda.synchronize()
+        order6[name + "_us_per_count"] = 1e6 * (time.perf_counter() - t_start) / 200
+    order6["count"] = int(c6.item())
+    del step6, d6, c6
+
     # ---------------- VS order 10, full count with symmetry breaking (Sec. 5.4) ----------------
     vs10 = None
     if not args.no_vs10:
@@ -297,6 +330,28 @@ def main():
                 "seconds": vwall, "leaves": vleaves, "leaves_per_s": vleaves / (vms * 1e-3),
                 "total": int(vt.item()), "exact": int(vt.item()) == VS10_FIXED and int(d_status.item()) == 0}
         del vd, vm, vc
+
+    # ---------------- order 8 end to end on the GPU: canonical classes + count ----------------
+    # diagonal designs split on the host, hourglass designs and their canonical
+    # forms on the GPU (Alg. 5), completions of the canonical designs counted
+    # on the GPU (the device expansion adds the depth the host split used to)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hpre, hmult = dls.hourglass_classes_gpu(n)
+    t1 = time.perf_counter()
+    hd = torch.from_numpy(hpre).to(dev)
+    hm = torch.from_numpy(hmult.astype(np.int32)).to(dev)
+    hc = torch.zeros(len(hpre), dtype=torch.int64, device=dev)
+    hpat = (hpre[0] != 0xFF).astype(np.uint8)
+    dls.dls_count_async_ex(n, 0, hpat, hd, len(hpre), hc, d_status, stream, launch_of(dls, {}, time_kernel=1))
+    dls.dls_reduce_weighted(hc, hm, len(hpre), d_total, stream)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    hms, _ = dls.dls_kernel_time_ms(stream)
+    end_to_end = {"classes": len(hpre), "classes_seconds": t1 - t0, "count_seconds": t2 - t1,
+                  "count_kernel_ms": hms, "seconds": t2 - t0,
+                  "exact": int(d_total.item()) == ORDER8_FIXED and int(d_status.item()) == 0}
+    del hd, hm, hc
 
     # ---------------- CPU oracle on a bounded sample of the same workload ----------------
     # The oracle builds its own sample: seeded canonical hourglasses (its own
@@ -353,7 +408,8 @@ def main():
                    "weighted_total": weighted, "parallelism": "single GPU",
                    "launch": tuned or "library defaults"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": measured_traffic()},
+                     "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": measured_traffic(),
+                     "measured_peak": measured_peak / 1e12, "frac_of_measured": achieved / measured_peak},
         "cpu_baseline": cpu,
         "plain_kernel": {"value": leaves / (results["plain"]["ms_per_step"] * 1e-3),
                          "ms_per_step": results["plain"]["ms_per_step"],
@@ -362,6 +418,8 @@ def main():
         "graph": graph,
         "order7_diag_split": order7,
         "vs_order10_full": vs10,
+        "order6_single_prefix": order6,
+        "order8_symbreak_end_to_end": end_to_end,
         "speedup_persistent_vs_plain": results["plain"]["ms_per_step"] / p["ms_per_step"],
         "effective_counted_per_s": weighted / (p["ms_per_step"] * 1e-3),
         "dfs_steps_per_launch": total_steps,
@@ -369,7 +427,7 @@ def main():
         "split_seconds_host": split_s,
         "sustained_full_count": sustained,
         "exact": (all(r["exact"] for r in results.values()) and all(g["exact"] for g in graph.values())
-                  and order7["exact"] and (vs10 is None or vs10["exact"])),
+                  and order7["exact"] and (vs10 is None or vs10["exact"]) and end_to_end["exact"]),
     }
     print(json.dumps(line))
 

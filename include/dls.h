@@ -208,6 +208,23 @@ int dls_count_cells_async(int n, uint32_t flags, const int *cells, int ncells,
                           int64_t num, uint64_t *d_counts, uint32_t *d_status,
                           void *stream, const dls_launch *launch);
 
+/*
+ * Hourglass designs and their canonical forms on the GPU (Sec. 4.2-4.3,
+ * Alg. 5), 4 <= n <= 9.  d_designs: [num][n*n] diagonal designs (row 0,
+ * main diagonal and antidiagonal assigned and consistent, every other cell
+ * 0xFF), e.g. dls_split_cells over the diagonal cells.  Every consistent
+ * filling of the rest of the last row makes an hourglass design; the
+ * canonical ones (no transformed and renamed image lexicographically
+ * smaller) are written to d_out [cap][n*n] with their class powers in
+ * d_mult [cap], in no particular order; *d_count (device uint64) receives
+ * their number.  If it exceeds cap, only cap designs are written and bit 3
+ * of *d_status is set: call again with a larger buffer.  Device buffers on
+ * `stream`; the first call for an order uploads the group table.
+ */
+int dls_hourglass_classes_async(int n, const uint8_t *d_designs, int64_t num, uint8_t *d_out,
+                                uint32_t *d_mult, int64_t cap, uint64_t *d_count,
+                                uint32_t *d_status, void *stream);
+
 /* Mean duration in milliseconds of the search kernels launched with
  * time_kernel on `stream` since the previous call (at most 65536 launches),
  * and their number in *launches_out (may be NULL).  Resets the tally.  The

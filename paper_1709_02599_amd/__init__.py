@@ -22,6 +22,7 @@ __all__ = [
     "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
     "dls_count_cells_async", "dls_split_cells", "dls_order_cost",
+    "dls_hourglass_classes_async", "hourglass_classes_gpu",
 ]
 
 DLS_VSYM = 1 << 0
@@ -99,6 +100,8 @@ def _load() -> ctypes.CDLL:
         "dls_order_cost": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                           u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64)]),
+        "dls_hourglass_classes_async": (ctypes.c_int, [ctypes.c_int, vp, ctypes.c_int64, vp, vp, ctypes.c_int64,
+                                                       vp, vp, vp]),
         "dls_count_cells": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
                                            ctypes.c_int, u8p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]),
         "dls_count_cells_async": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int),
@@ -354,3 +357,47 @@ def dls_order_cost(n: int, flags: int, cells, prefixes):
            "dls_order_cost")
     del keep
     return int(st.value), int(lv.value)
+
+
+def dls_hourglass_classes_async(n: int, d_designs, num: int, d_out, d_mult, cap: int, d_count,
+                                d_status=None, stream=None) -> None:
+    _check(_lib.dls_hourglass_classes_async(n, _ptr(d_designs), num, _ptr(d_out), _ptr(d_mult), cap,
+                                            _ptr(d_count), _ptr(d_status), _stream(stream)),
+           "dls_hourglass_classes_async")
+
+
+def diagonal_cells(n: int) -> list:
+    """Cells of both diagonals outside row 0, row-major."""
+    return [c for c in range(n, n * n) if c // n == c % n or c // n + c % n == n - 1]
+
+
+def hourglass_classes_gpu(n: int, stream=None):
+    """Canonical hourglass designs of order n and their class powers,
+    computed on the GPU from the diagonal designs (split on the host).
+    Returns (designs [P, n*n] uint8, powers [P] uint32) sorted
+    lexicographically."""
+    import torch
+    base = np.full(n * n, DLS_EMPTY, dtype=np.uint8)
+    base[:n] = np.arange(n, dtype=np.uint8)
+    designs = dls_split_cells(n, 0, base, diagonal_cells(n))
+    dev = torch.device("cuda:0")
+    d_des = torch.from_numpy(designs).to(dev)
+    d_cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    d_st = torch.zeros(1, dtype=torch.int32, device=dev)
+    cap = max(1024, len(designs))
+    while True:
+        d_out = torch.empty((cap, n * n), dtype=torch.uint8, device=dev)
+        d_mult = torch.empty(cap, dtype=torch.int32, device=dev)
+        d_st.zero_()
+        dls_hourglass_classes_async(n, d_des, len(designs), d_out, d_mult, cap, d_cnt, d_st, stream)
+        torch.cuda.synchronize()
+        found = int(d_cnt.item())
+        if found <= cap:
+            break
+        cap = found
+    if int(d_st.item()) & ~8:
+        raise DLSError(-4, f"hourglass classes: device status {int(d_st.item())}")
+    out = d_out[:found].cpu().numpy()
+    mult = d_mult[:found].cpu().numpy().view(np.uint32).copy()
+    order = np.lexsort(out.T[::-1])
+    return out[order], mult[order]

@@ -14,7 +14,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdls.so")
 ARCH = "gfx950"
 
-SOURCES = ["dls_host.cpp", "dls_api.cpp", "dls_kernels.hip"]
+SOURCES = ["dls_host.cpp", "dls_api.cpp", "dls_kernels.hip", "dls_canon.hip"]
 
 # all HIP code is built with packed FP32 instructions disabled (the kernels
 # use none; the flag keeps the compiler from forming them on its own)

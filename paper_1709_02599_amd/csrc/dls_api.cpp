@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/dls.h"
+#include "dls_canon.hpp"
 #include "dls_host.hpp"
 #include "dls_kernels.hpp"
 
@@ -104,10 +105,18 @@ bool capturing(void *stream) {
     return hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
+// hourglass group of one order on one device (table and cell list)
+struct CanonTables {
+    uint8_t *tab = nullptr;
+    uint8_t *hc = nullptr;
+    int groups = 0, kcells = 0;
+};
+
 struct DeviceState {
     bool init = false;
     int cus = 0;
     std::map<void *, QueueSlot> slots;  // scratch and work queue per stream
+    std::map<int, CanonTables> canon;   // per order
 };
 
 std::mutex g_dev_mu;
@@ -666,6 +675,56 @@ int dls_count_cells_async(int n, uint32_t flags, const int *cells, int ncells, c
     static const int none = 0;
     return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, launch, nullptr,
                             cells ? cells : &none, ncells);
+}
+
+int dls_hourglass_classes_async(int n, const uint8_t *d_designs, int64_t num, uint8_t *d_out, uint32_t *d_mult,
+                                int64_t cap, uint64_t *d_count, uint32_t *d_status, void *stream) {
+    if (n < 4 || n > 9 || num < 0 || cap < 0 || !d_count || (num > 0 && !d_designs)) return DLS_EINVAL;
+    if (cap > 0 && (!d_out || !d_mult)) return DLS_EINVAL;
+    if (capturing(stream)) return DLS_ECAPTURE;
+    DeviceState *ds = nullptr;
+    int dev = 0;
+    int rc = device_state(&ds, &dev);
+    if (rc) return rc;
+    CanonTables *ct = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        auto it = ds->canon.find(n);
+        if (it == ds->canon.end()) {
+            dls::HourglassGroup g(n);
+            std::vector<uint8_t> tab = g.src_table();
+            std::vector<uint8_t> hc;
+            for (int c : g.cells()) hc.push_back((uint8_t)c);
+            CanonTables t;
+            t.groups = g.size();
+            t.kcells = (int)hc.size();
+            if (hipMalloc((void **)&t.tab, tab.size()) != hipSuccess) return DLS_ENOMEM;
+            if (hipMalloc((void **)&t.hc, hc.size()) != hipSuccess) return DLS_ENOMEM;
+            hipError_t e = hipMemcpy(t.tab, tab.data(), tab.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(t.hc, hc.data(), hc.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+            it = ds->canon.emplace(n, t).first;
+        }
+        ct = &it->second;
+    }
+    if (dlsc::canon_lds_bytes(n, ct->groups, ct->kcells) > 64 * 1024) return DLS_EINVAL;
+    dlsc::CanonArgs a;
+    a.n = n;
+    a.designs = d_designs;
+    a.num = num;
+    a.src_tab = ct->tab;
+    a.groups = ct->groups;
+    a.kcells = ct->kcells;
+    a.hc = ct->hc;
+    a.out = d_out;
+    a.out_mult = d_mult;
+    a.cap = cap;
+    a.out_count = reinterpret_cast<unsigned long long *>(d_count);
+    a.status = d_status;
+    a.stream = (hipStream_t)stream;
+    hipError_t e = dlsk::launch_zero(d_count, 1, a.stream);
+    if (e == hipSuccess) e = dlsc::launch_canon(a);
+    return e == hipSuccess ? DLS_OK : hip_fail(e, DLS_EDEVICE);
 }
 
 int dls_kernel_time_ms(void *stream, float *ms_out, int64_t *launches_out) {

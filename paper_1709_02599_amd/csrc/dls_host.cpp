@@ -247,6 +247,16 @@ HourglassGroup::HourglassGroup(int n) : n_(n) {
     }
 }
 
+std::vector<uint8_t> HourglassGroup::src_table() const {
+    std::vector<int> pos((size_t)n_ * n_, -1);
+    for (size_t k = 0; k < hc_.size(); ++k) pos[hc_[k]] = (int)k;
+    std::vector<uint8_t> t;
+    t.reserve(src_.size() * hc_.size());
+    for (const auto &src : src_)
+        for (int c : src) t.push_back((uint8_t)pos[c]);
+    return t;
+}
+
 uint32_t HourglassGroup::canon(const uint8_t *h) const {
     const int n = n_;
     int stab = 0;

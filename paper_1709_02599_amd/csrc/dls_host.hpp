@@ -59,6 +59,11 @@ class HourglassGroup {
     uint32_t canon(const uint8_t *h) const;
     // image of h under element g (renormalised by row 0), for tests.
     void apply(int g, const uint8_t *h, uint8_t *out) const;
+    // the group as a table [size()][cells().size()]: entry (g, k) is the
+    // index (into cells()) of the hourglass cell whose value lands on
+    // hourglass cell k under g
+    std::vector<uint8_t> src_table() const;
+    const std::vector<int> &cells() const { return hc_; }
 
   private:
     int n_;

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "dls_kernels.hpp"
@@ -794,8 +795,9 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
-// Inclusive sum over the workgroup (256 threads, 4 waves); *total gets the
-// workgroup's sum.  Uses part[4] of LDS; every thread must call it.
+// Inclusive sum over the workgroup (W waves of 64 lanes); *total gets the
+// workgroup's sum.  Uses part[W] of LDS; every thread must call it.
+template <int W = 4>
 __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *part, uint32_t *total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t x = v;
@@ -808,7 +810,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *part, uint3
     __syncthreads();
     uint32_t before = 0, all = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < W; ++k) {
         const uint32_t q = part[k];
         before += k < w ? q : 0u;
         all += q;
@@ -845,8 +847,9 @@ struct RunSum {
         }
     }
 
-    // one atomic per run left in the workgroup's four waves (runs of equal
+    // one atomic per run left in the workgroup's W waves (runs of equal
     // prefixes merged); every thread must call it
+    template <int W = 4>
     __device__ __forceinline__ void flush(uint64_t *ucounts, uint32_t *so, uint64_t *sv) {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         if (lane == 0) {
@@ -857,7 +860,7 @@ struct RunSum {
         if (threadIdx.x == 0) {
             uint32_t co = 0xFFFFFFFFu;
             uint64_t cv = 0;
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < W; ++k) {
                 if (!sv[k]) continue;
                 if (so[k] != co) {
                     if (cv) atomicAdd((unsigned long long *)&ucounts[co], (unsigned long long)cv);
@@ -1032,6 +1035,84 @@ __global__ void __launch_bounds__(256) ex_write(const Plan plan, Expand *E2, int
     acc.flush(ucounts, so, sv);
 }
 
+// The narrow first levels of a small batch, all inside one workgroup of
+// 1024 lanes: each level is processed in chunks of 1024 tasks with a
+// workgroup scan placing the children, so a level costs a few microseconds
+// instead of two kernel launches.  Runs from state 0 until the batch has
+// `limit` tasks (the multi-workgroup passes take over from there), reaches
+// the target, or has no live task left, and leaves the result in state 0.
+// The host keeps N * limit <= cap, so a level always fits the buffers.
+template <int N, bool VS>
+__global__ void __launch_bounds__(1024) ex_small(const Plan plan, Expand *E2, void *buf1, void *buf2,
+                                                 uint32_t *orig1, uint32_t *orig2, uint64_t *ucounts,
+                                                 uint64_t *tcounts, uint32_t *status, int64_t target, int64_t cap,
+                                                 int64_t limit, int max_passes) {
+    using R = Rec<N, VS>;
+    constexpr int W = 16;
+    __shared__ uint32_t sdesc[kMaxLevels];
+    __shared__ uint32_t part[W];
+    __shared__ uint32_t so[W];
+    __shared__ uint64_t sv[W];
+    const int nlev = plan.nlev;
+    for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
+    __syncthreads();
+    const int last = nlev - 1;
+    Expand e = E2[0];
+    RunSum acc;
+    for (int p = 0; p < max_passes && !e.stop && e.num < target && e.num < limit; ++p) {
+        const int cur = e.cur;
+        R *out = reinterpret_cast<R *>(cur == 1 ? buf2 : buf1);
+        uint32_t *oorig = cur == 1 ? orig2 : orig1;
+        const R *in = reinterpret_cast<const R *>(e.recs);
+        uint64_t run = 0;
+        for (int64_t chunk = 0; chunk < e.num; chunk += blockDim.x) {  // uniform
+            const int64_t i = chunk + threadIdx.x;
+            Kids<N, VS> k;
+            if (i < e.num) k.load(in, e.orig, i, sdesc, last);
+            uint32_t step = 0;
+            const uint32_t incl = block_scan<W>(k.kids, part, &step);
+            uint64_t pos = run + (incl - k.kids);
+            run += step;
+            if (k.kids) {
+                const uint32_t dc = sdesc[k.lvl], dn = sdesc[k.lvl + 1];
+                for (uint32_t c = k.cand; c; c &= c - 1u) {
+                    Lane<N, VS> T = k.L;
+                    T.toggle(dc, c & (0u - c));
+                    const uint32_t nc = T.cands(dn);
+                    if (!nc) continue;
+                    if (pos >= (uint64_t)cap) {  // cannot happen: N * limit <= cap
+                        if (status) atomicOr(status, 4u);
+                        break;
+                    }
+                    R o;
+#pragma unroll
+                    for (int w = 0; w < Geo<N, VS>::WR; ++w) o.R[w] = T.R[w];
+#pragma unroll
+                    for (int w = 0; w < Geo<N, VS>::WC; ++w) o.C[w] = T.C[w];
+                    o.diag = T.md | (T.ad << 16);
+                    o.cl = nc | ((k.lvl + 1u) << 16);
+                    o.origin = (uint32_t)pos;
+                    o.pad = 0;
+                    out[pos] = o;
+                    oorig[pos] = k.orig;
+                    tcounts[pos] = 0;
+                    ++pos;
+                }
+            }
+            acc.add(k.orig, k.leaves, ucounts);
+        }
+        __syncthreads();  // this level's children are written before they are read
+        e.recs = out;
+        e.orig = oorig;
+        e.cur = cur == 1 ? 2 : 1;
+        e.num = (int64_t)run;
+        e.counts = tcounts;
+        e.stop = run == 0;
+    }
+    acc.flush<W>(ucounts, so, sv);
+    if (threadIdx.x == 0) E2[0] = e;
+}
+
 // add the expanded tasks' counts to their prefixes
 __global__ void __launch_bounds__(256) ex_scatter(const Expand *E, uint64_t *ucounts) {
     __shared__ uint32_t so[4];
@@ -1143,6 +1224,11 @@ static hipError_t launch_n(const LaunchArgs &a) {
         const bool expand = a.ex != nullptr && a.plan.nlev >= 3;
         if (expand) {
             hipLaunchKernelGGL(ex_init, dim3(1), dim3(64), 0, a.stream, a.ex, a.records, a.num, a.counts);
+            const int64_t limit = std::min<int64_t>(4096, a.ecap / 16);
+            if (limit > 0)
+                hipLaunchKernelGGL((ex_small<N, VS>), dim3(1), dim3(1024), 0, a.stream, a.plan, a.ex, a.ebuf[0],
+                                   a.ebuf[1], a.eorig[0], a.eorig[1], a.counts, a.tcounts, a.status, a.etarget,
+                                   a.ecap, limit, a.plan.nlev - 2);
             for (int p = 0; p < a.epasses; ++p) {
                 hipLaunchKernelGGL((ex_tally<N, VS>), dim3(kExBlocks), dim3(256), 0, a.stream, a.plan, a.ex, p,
                                    a.eblk);
