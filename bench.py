@@ -60,7 +60,8 @@ OPS_PER_DOWN_STEP = 12
 OPS_PER_TASK = 3
 
 
-LAUNCH_FIELDS = ("block", "refill_every", "order_variant", "expand_target", "chunk_min", "steal_depth")
+LAUNCH_FIELDS = ("block", "refill_every", "order_variant", "expand_target", "chunk_min", "steal_depth",
+                 "lds_masks")
 
 
 def tuned_launch(n, flags, workload):

@@ -186,6 +186,10 @@ typedef struct {
     int chunk_min;      /* persistent kernel: smallest number of tasks a
                            wave takes from the static queue at once
                            (0 = default 8; at most 65536)                  */
+    int lds_masks;      /* persistent kernel: positive = keep the row and
+                           column masks of each lane in LDS (one xor per
+                           line to mark a value) instead of packed VGPR
+                           words; 0 / negative = VGPR layout (default)    */
 } dls_launch;
 
 /*

@@ -69,7 +69,7 @@ def best(n: int, flags: int, workload: str, arch: Optional[str] = None) -> Optio
 
 
 FIELDS = ("block", "blocks_per_cu", "steal_depth", "refill_every", "order_variant", "time_kernel",
-          "expand_target", "chunk_min")
+          "expand_target", "chunk_min", "lds_masks")
 
 
 def _launch(settings: dict, time_kernel: int = 0) -> DlsLaunch:
@@ -191,11 +191,13 @@ def main(argv=None):
 
     if want("order8-symbreak-row1"):
         pre, mult = dls_split(8, DLS_SYMBREAK, 26)
-        r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps)
+        r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
+                 space={"order_variant": VARIANTS, "block": BLOCKS, "refill_every": REFILLS, "lds_masks": (0, 1)},
+                 default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": 0})
         print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
                           "plain_ms": r["plain_ms"]}), flush=True)
         d = tune_depth(8, DLS_SYMBREAK, (20, 22, 24, 26, 27, 28), "order8-symbreak",
-                       launch={k: r["best"][k] for k in ("block", "refill_every", "order_variant")},
+                       launch={k: r["best"][k] for k in ("block", "refill_every", "order_variant", "lds_masks")},
                        reps=args.reps)
         print(json.dumps({"workload": "order8-symbreak", "depths": d["table"]}), flush=True)
     if want("order7-diag11"):

@@ -91,6 +91,17 @@ template <class T>
 __device__ __forceinline__ void lds_st(uint32_t a, T v) {
     *reinterpret_cast<__attribute__((address_space(3))) T *>((uintptr_t)a) = v;
 }
+// 16-byte LDS load (one ds_read_b128)
+__device__ __forceinline__ uint4 lds_ld4(uint32_t a) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const v4u v = *reinterpret_cast<const __attribute__((address_space(3))) v4u *>((uintptr_t)a);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <class T>
+__device__ __forceinline__ void lds_xor(uint32_t a, T v) {
+    __hip_atomic_fetch_xor(reinterpret_cast<__attribute__((address_space(3))) T *>((uintptr_t)a), v,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 // LDS address of a __shared__ object
 __device__ __forceinline__ uint32_t lds_of(const void *p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
@@ -215,6 +226,168 @@ constexpr uint32_t kStackBase = sizeof(uint32_t) * kMaxLevels;
 __host__ __device__ inline uint32_t mailbox_offset(int nlev, int block, int elem) {
     const uint32_t end = kStackBase + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
     return (end + 15u) & ~15u;
+}
+
+// LDS layout with the line masks in LDS (LdsLane): a table of 16-byte level
+// descriptors, then the row and column masks (one 32-bit word per line and
+// lane, lines apart by `lstride` = 4 * block bytes, lanes side by side), then
+// the stacks, then the mailboxes.
+constexpr uint32_t kLmDescBytes = 16u * kMaxLevels;
+
+__host__ __device__ inline uint32_t lm_stack_base(int lines, int block) {
+    return kLmDescBytes + 4u * (uint32_t)lines * (uint32_t)block;
+}
+
+__host__ __device__ inline uint32_t lm_mailbox_offset(int lines, int nlev, int block, int elem) {
+    const uint32_t end = lm_stack_base(lines, block) + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
+    return (end + 15u) & ~15u;
+}
+
+// Lane state with the row and column masks in LDS instead of VGPRs.  A value
+// is marked or cleared with one LDS xor per line (ds_xor_b32), so the packed
+// 64-bit words and their word selection disappear from the search loop;
+// only the diagonal masks stay in registers.  The level descriptor is 16
+// bytes: LDS offsets of the cell's row and column mask words and the
+// diagonal selectors as all-ones / zero masks.
+template <int N, bool VS>
+struct LdsLane {
+    using G = Geo<N, VS>;
+    static constexpr int LINES = N + G::NCOL;
+    uint32_t md, ad;    // diagonal masks
+    uint32_t cand;      // remaining candidates at the current level
+    uint32_t da;        // LDS address of the current level's descriptor (base + 16 * level)
+    uint32_t da0;       // the same for the level at which this task began
+    uint32_t sa;        // LDS address of this lane's stack entry for the current level
+    uint32_t mbase;     // LDS address of this lane's row-0 mask word
+    uint32_t c32;       // squares completed since the last flush()
+    uint64_t cnt;       // squares completed by this task (after flush())
+
+    __device__ __forceinline__ int depth(uint32_t dbase) const { return (int)((da - dbase) >> 4); }
+    __device__ __forceinline__ int start_level(uint32_t dbase) const { return (int)((da0 - dbase) >> 4); }
+    __device__ __forceinline__ void flush() {
+        cnt += c32;
+        c32 = 0u;
+    }
+    __device__ __forceinline__ bool done() const { return cand == 0u && da == da0; }
+
+    // mark or clear the value bit b at the cell of descriptor t; md/ad are
+    // the diagonal masks to update
+    __device__ __forceinline__ void toggle_at(const uint4 &t, uint32_t b, uint32_t &dmd, uint32_t &dad) const {
+        if constexpr (VS) {
+            const uint32_t rb = (1u << (N - 1)) >> (__builtin_ctz(b) & 31u);  // N-1-v
+            lds_xor(mbase + t.x, b | rb);
+            lds_xor(mbase + t.y, b);
+            dmd ^= (b & t.z) | (rb & t.w);
+            dad ^= (b & t.w) | (rb & t.z);
+        } else {
+            lds_xor(mbase + t.x, b);
+            lds_xor(mbase + t.y, b);
+            dmd ^= b & t.z;
+            dad ^= b & t.w;
+        }
+    }
+
+    template <class S>
+    __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last) {
+        const bool up = (cand == 0u);
+        const uint32_t nda = da + (up ? 0u - 16u : 16u);
+        const uint32_t nsa = sa + (up ? 0u - stride : stride);
+        const uint4 nd = lds_ld4(nda);
+        const uint4 td = lds_ld4(up ? nda : da);  // the cell whose value is marked or cleared
+        const uint32_t saved = lds_ld<S>(up ? nsa : sa);
+        lds_st<S>(sa, (S)cand);  // up lanes write 0 into a slot nobody reads again
+        const uint32_t stored = up ? saved : cand;
+        const uint32_t b = stored & (0u - stored);
+        toggle_at(td, b, md, ad);
+        const uint32_t r = lds_ld<uint32_t>(mbase + nd.x), c = lds_ld<uint32_t>(mbase + nd.y);
+        const uint32_t nc = G::ALL & ~(r | c | (md & nd.z) | (ad & nd.w));
+        const bool leaf = (nda == da_last);
+        c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
+        cand = up ? (stored ^ b) : (leaf ? 0u : nc);
+        da = nda;
+        sa = nsa;
+    }
+
+    // Start the task of record r: its masks go to this lane's LDS words.
+    __device__ __forceinline__ void from_rec(const Rec<N, VS> &r, uint32_t dbase, int last, uint32_t lane_off,
+                                             uint32_t stride, uint32_t lstride) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            lds_st<uint32_t>(mbase + (uint32_t)i * lstride,
+                             (uint32_t)(r.R[i / G::LPW] >> ((i % G::LPW) * N)) & G::ALL);
+#pragma unroll
+        for (int j = 0; j < G::NCOL; ++j)
+            lds_st<uint32_t>(mbase + (uint32_t)(N + j) * lstride,
+                             (uint32_t)(r.C[j / G::LPW] >> ((j % G::LPW) * N)) & G::ALL);
+        md = r.diag & 0xFFFFu;
+        ad = r.diag >> 16;
+        cnt = 0;
+        c32 = 0u;
+        const uint32_t lvl = r.cl >> 16;
+        if (lvl == kNone) {
+            cand = 0u;
+            da = da0 = dbase;
+            sa = lane_off;
+            return;
+        }
+        cand = r.cl & 0xFFFFu;
+        da = da0 = dbase + 16u * lvl;
+        sa = lane_off + lvl * stride;
+        if ((int)lvl == last) {
+            c32 = (uint32_t)__builtin_popcount(cand);
+            cand = 0u;
+        }
+    }
+
+    // Give away the untried siblings at level lvl (see donate()): the masks
+    // are rewound in place to lvl, copied into the record, then replayed.
+    template <class SlotOf>
+    __device__ __forceinline__ Rec<N, VS> donate(int lvl, uint32_t dbase, SlotOf slot_of, uint32_t origin,
+                                                 uint32_t lstride) const {
+        const int dep = depth(dbase);
+        uint32_t tmd = md, tad = ad;
+        for (int l = dep - 1; l >= lvl; --l) {
+            const uint32_t sv = *slot_of(l);
+            toggle_at(lds_ld4(dbase + 16u * (uint32_t)l), sv & (0u - sv), tmd, tad);
+        }
+        Rec<N, VS> r;
+#pragma unroll
+        for (int k = 0; k < G::WR; ++k) r.R[k] = 0;
+#pragma unroll
+        for (int k = 0; k < G::WC; ++k) r.C[k] = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            r.R[i / G::LPW] |= (uint64_t)lds_ld<uint32_t>(mbase + (uint32_t)i * lstride) << ((i % G::LPW) * N);
+#pragma unroll
+        for (int j = 0; j < G::NCOL; ++j)
+            r.C[j / G::LPW] |= (uint64_t)lds_ld<uint32_t>(mbase + (uint32_t)(N + j) * lstride) << ((j % G::LPW) * N);
+        uint32_t rmd = tmd, rad = tad;
+        for (int l = lvl; l < dep; ++l) {  // replay: this lane keeps its branch
+            const uint32_t sv = *slot_of(l);
+            toggle_at(lds_ld4(dbase + 16u * (uint32_t)l), sv & (0u - sv), rmd, rad);
+        }
+        const uint32_t sv = *slot_of(lvl);
+        const uint32_t b = sv & (0u - sv);
+        r.diag = tmd | (tad << 16);
+        r.cl = (sv ^ b) | ((uint32_t)lvl << 16);
+        r.origin = origin;
+        r.pad = 0;
+        *slot_of(lvl) = (decltype(*slot_of(lvl) + 0))b;
+        return r;
+    }
+};
+
+// descriptor table of the LDS-mask layout from the plan (one entry per level)
+template <int N, bool VS>
+__device__ __forceinline__ void lm_build_desc(const Plan &plan, unsigned char *smem, uint32_t lstride) {
+    using G = Geo<N, VS>;
+    uint4 *t = reinterpret_cast<uint4 *>(smem);
+    for (int k = threadIdx.x; k < plan.nlev; k += blockDim.x) {
+        const uint32_t d = plan.desc[k];
+        const uint32_t i = ((d >> 6) & 3u) * G::LPW + (d & 63u) / N;
+        const uint32_t j = ((d >> 14) & 3u) * G::LPW + ((d >> 8) & 63u) / N;
+        t[k] = make_uint4(i * lstride, (N + j) * lstride, d_md(d), d_ad(d));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -422,12 +595,15 @@ __device__ __forceinline__ Rec<N, VS> donate(const Lane<N, VS> &L, int lvl, cons
 constexpr int kWaitVm1 = 0x0F71;
 constexpr int kWaitVm0 = 0x0F70;
 
-template <int N, bool VS, bool STATS>
+template <int N, bool VS, bool STATS, bool LM>
 __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const Rec<N, VS> *recs, int64_t num,
                                                           uint64_t *counts, uint32_t *status, uint64_t *steps,
                                                           Ctrl *ctrl, Rec<N, VS> *items, uint32_t *ready,
                                                           int64_t item_cap, Tuning tune, const Expand *ex) {
     using S = StackT<N>;
+    // LM: line masks in LDS (LdsLane), else in VGPRs (Lane)
+    using LaneT = typename std::conditional<LM, LdsLane<N, VS>, Lane<N, VS>>::type;
+    constexpr int LINES = N + Geo<N, VS>::NCOL;
     if (ex) {
         // the batch as the expansion passes left it
         recs = reinterpret_cast<const Rec<N, VS> *>(ex->recs);
@@ -437,15 +613,21 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *sdesc = reinterpret_cast<uint32_t *>(smem);
     const int nlev = plan.nlev;
-    for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
+    const uint32_t lstride = blockDim.x * 4u;  // LM: bytes between two lines' mask words
+    if constexpr (LM) {
+        lm_build_desc<N, VS>(plan, smem, lstride);
+    } else {
+        for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const bool poller = (threadIdx.x >> 6) == 0;  // one wave per workgroup waits for donations
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t dbase = lds_of(smem);
-    const uint32_t loff = kStackBase + threadIdx.x * (uint32_t)sizeof(S);  // from smem
-    const uint32_t lane_off = dbase + loff;                                   // LDS address
+    const uint32_t sbase = LM ? lm_stack_base(LINES, blockDim.x) : kStackBase;
+    const uint32_t loff = sbase + threadIdx.x * (uint32_t)sizeof(S);  // from smem
+    const uint32_t lane_off = dbase + loff;                             // LDS address
     const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
     auto slot_of = [&](int l) -> S * { return reinterpret_cast<S *>(smem + (loff + (uint32_t)l * stride)); };
     const int last = nlev - 1;
@@ -461,15 +643,25 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     if (global && lane == 0) atomicAdd((unsigned long long *)&ctrl->busy, 1ull);
     bool marked = global;
 
-    Lane<N, VS> L;
+    LaneT L;
     L.cand = 0u;
     L.da = L.da0 = dbase;
     L.sa = lane_off;
     L.cnt = 0;
     L.c32 = 0u;
-    const uint32_t da_last = dbase + 4u * (uint32_t)last;
+    if constexpr (LM) L.mbase = dbase + kLmDescBytes + threadIdx.x * 4u;
+    const uint32_t da_last = dbase + (LM ? 16u : 4u) * (uint32_t)last;
     bool has = false;           // lane holds a task (possibly finished)
     uint64_t *out = &ctrl->sink;  // where this lane's task count goes (a sink until the first task)
+    // start the task of a record / give away part of this lane's task
+    auto start = [&](const Rec<N, VS> &r) {
+        if constexpr (LM) L.from_rec(r, dbase, last, lane_off, stride, lstride);
+        else L.from_rec(r, sdesc, last, dbase, lane_off, stride);
+    };
+    auto give = [&](int lvl) -> Rec<N, VS> {
+        if constexpr (LM) return L.donate(lvl, dbase, slot_of, (uint32_t)(out - counts), lstride);
+        else return donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts), dbase);
+    };
     uint64_t stored = 0;        // part of L.cnt already in *out
     bool static_left = true;    // wave-uniform
     uint64_t cb = 0, ce = 0;    // wave-private range of static tasks
@@ -477,7 +669,9 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     uint64_t seen_sig = ~0ull, seen_at = 0;
     uint32_t backoff = 1, tick = 0;
     bool asked = false;         // this (idle poller) wave is counted in ctrl->hungry
-    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(smem + mailbox_offset(nlev, blockDim.x, sizeof(S))) +
+    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(
+                           smem + (LM ? lm_mailbox_offset(LINES, nlev, blockDim.x, sizeof(S))
+                                      : mailbox_offset(nlev, blockDim.x, sizeof(S)))) +
                        (threadIdx.x & ~63u);
 
     for (;;) {
@@ -538,7 +732,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                 __builtin_amdgcn_s_waitcnt(kWaitVm1);
                 if (fin) has = false;
                 if (my_id >= 0) {
-                    L.from_rec(r, sdesc, last, dbase, lane_off, stride);
+                    start(r);
                     out = &counts[r.origin];
                     stored = 0;
                     has = true;
@@ -580,14 +774,14 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                 const uint64_t drank = (uint64_t)__popcll(donors & below);
                 const uint64_t rrank = (uint64_t)__popcll(want & below);
                 if (lvl >= 0 && drank < m) {
-                    const Rec<N, VS> r = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts), dbase);
+                    const Rec<N, VS> r = give(lvl);
                     mbox[drank] = r;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 if (!has && rrank < m) {
                     const Rec<N, VS> r = mbox[rrank];
-                    L.from_rec(r, sdesc, last, dbase, lane_off, stride);
+                    start(r);
                     out = &counts[r.origin];
                     stored = 0;
                     has = true;
@@ -665,7 +859,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
                         __threadfence();
                         const Rec<N, VS> r = items[slot];
                         __hip_atomic_store(&ready[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        L.from_rec(r, sdesc, last, dbase, lane_off, stride);
+                        start(r);
                         out = &counts[r.origin];
                         stored = 0;
                         has = true;
@@ -728,7 +922,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
             if (lvl >= 0 && (uint64_t)__popcll(donors & below) < quota) {
                 const uint64_t slot = atomicAdd((unsigned long long *)&ctrl->dq_reserve, 1ull);
                 if (slot < cap) {
-                    items[slot] = donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts), dbase);
+                    items[slot] = give(lvl);
                     __threadfence();
                     __hip_atomic_store(&ready[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
@@ -1208,7 +1402,7 @@ static hipError_t launch_n(const LaunchArgs &a) {
     using R = Rec<N, VS>;
     (void)hipGetLastError();  // drop an error left by an unrelated earlier call
     const int block = a.block;
-    const size_t lds = lds_bytes(N, VS, a.plan.nlev, block, a.persistent);
+    const size_t lds = lds_bytes(N, VS, a.plan.nlev, block, a.persistent, a.persistent && a.tune.lds_masks);
     R *recs = reinterpret_cast<R *>(a.records);
     const unsigned pgrid = (unsigned)((a.num + 255) / 256);
     hipLaunchKernelGGL((prep_kernel<N, VS>), dim3(pgrid), dim3(256), 0, a.stream, a.plan, a.prefixes, a.num, recs,
@@ -1239,14 +1433,17 @@ static hipError_t launch_n(const LaunchArgs &a) {
         }
         // the state after the last pass
         const Expand *ex = expand ? a.ex + (a.epasses & 1) : nullptr;
-        if (a.steps)
-            hipLaunchKernelGGL((persistent_kernel<N, VS, true>), dim3(a.grid), dim3(block), lds, a.stream, a.plan,
-                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune,
-                               ex);
-        else
-            hipLaunchKernelGGL((persistent_kernel<N, VS, false>), dim3(a.grid), dim3(block), lds, a.stream, a.plan,
-                               recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune,
-                               ex);
+#define DLS_PERSISTENT(STATS, LM)                                                                              \
+    hipLaunchKernelGGL((persistent_kernel<N, VS, STATS, LM>), dim3(a.grid), dim3(block), lds, a.stream, a.plan, recs, \
+                       a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune, ex)
+        if (a.tune.lds_masks) {
+            if (a.steps) DLS_PERSISTENT(true, true);
+            else DLS_PERSISTENT(false, true);
+        } else {
+            if (a.steps) DLS_PERSISTENT(true, false);
+            else DLS_PERSISTENT(false, false);
+        }
+#undef DLS_PERSISTENT
         if (expand) hipLaunchKernelGGL(ex_scatter, dim3(kExBlocks), dim3(256), 0, a.stream, ex, a.counts);
     } else {
         const int64_t grid = (a.num + block - 1) / block;
@@ -1310,9 +1507,13 @@ uint32_t make_desc(int n, bool vs, int i, int j) {
     return d;
 }
 
-size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent) {
+size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent, bool lds_masks) {
     const int elem = n <= 8 ? 1 : 2;
     if (!persistent) return kStackBase + (size_t)elem * (size_t)(nlev > 1 ? nlev : 1) * block;
+    if (lds_masks) {
+        const int lines = n + (vs ? (n + 1) / 2 : n);
+        return lm_mailbox_offset(lines, nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
+    }
     return mailbox_offset(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
 }
 

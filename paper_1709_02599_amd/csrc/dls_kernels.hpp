@@ -64,6 +64,7 @@ struct Tuning {
     int donate_low;    // donate while fewer donated tasks than this are queued
     int tail_poll;     // tail: read the queue state every tail_poll passes (power of 2)
     int chunk_min;     // smallest static chunk a wave takes from the queue
+    int lds_masks;     // nonzero: row and column masks in LDS (LdsLane) instead of VGPRs
 };
 
 // Size in bytes of one task record (packed masks of a partial square plus
@@ -109,6 +110,6 @@ hipError_t launch_valu_probe(int blocks, int iters, uint32_t *sink, hipStream_t 
 hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream);
 hipError_t launch_reduce_weighted(const uint64_t *counts, const uint32_t *mult, int64_t num, uint64_t *out,
                                   hipStream_t stream);
-size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent);
+size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent, bool lds_masks = false);
 
 }  // namespace dlsk

@@ -358,3 +358,43 @@ def test_vs_order10_full_count_with_symmetry_breaking():
     # element-wise parity on seeded positions the oracle counts one by one
     pos = workloads.sample_positions(len(pre), 24, seed=1054)
     assert np.array_equal(c[a][pos], oracle.count_many(n, opre[b][pos], vs=True))
+
+
+# --------------------------------------------------------------------------
+# line masks in LDS (LdsLane) instead of VGPRs
+# --------------------------------------------------------------------------
+
+LDS_MASKS = {"lds_masks": 1}
+
+
+@pytest.mark.parametrize("n,vs", [(4, False), (5, False), (6, False), (7, False), (6, True), (8, True)])
+def test_lds_masks_single_prefix(n, vs):
+    p = oracle.identity_prefix(n)
+    for launch in ({**LDS_MASKS, "expand_target": -1}, LDS_MASKS):
+        c, st = gpu_counts(dls, n, dls.DLS_VSYM if vs else 0, p[None], launch=launch)
+        assert st == 0 and int(c[0]) == oracle.count(n, p, vs=vs), launch
+
+
+@pytest.mark.parametrize("block", [64, 256, 512])
+def test_lds_masks_order7_split_and_donation(block):
+    pre, _ = dls.dls_split(7, 0, 8)
+    want = oracle.count_many(7, _oracle_split(7, False, 8))
+    for extra in ({}, {"steal_depth": 4, "expand_target": -1, "refill_every": 4}):
+        c, st = gpu_counts(dls, 7, 0, pre, launch={**LDS_MASKS, "block": block, **extra})
+        assert st == 0 and np.array_equal(c, want), (block, extra)
+
+
+def test_lds_masks_order8_symbreak(order8_symbreak):
+    pre, mult, opre, omult, a, b = order8_symbreak
+    c1, s1 = gpu_counts(dls, 8, 0, pre, launch=LDS_MASKS)
+    c2, s2 = gpu_counts(dls, 8, 0, pre, launch={**LDS_MASKS, "block": 512, "order_variant": 5})
+    c0, s0 = gpu_counts(dls, 8, 0, pre)
+    assert s0 == s1 == s2 == 0
+    assert np.array_equal(c1, c0) and np.array_equal(c2, c0)
+    assert weighted_total(c1, mult) == golden_io.counts()[(8, "fixed")]
+
+
+def test_lds_masks_vs_order10_sample():
+    total, cells, pos, opre, ocounts = golden_io.vs10_sample()
+    c, st = gpu_counts(dls, 10, dls.DLS_VSYM, opre[:512], launch=LDS_MASKS)
+    assert st == 0 and np.array_equal(c, ocounts[:512])
