@@ -33,9 +33,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "order8_symbreak_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1709_02599_amd", "csrc", "dls_kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(launch):
     """HBM bytes per launch from the committed counter summary, or None when
-    the kernel source has changed since the counters were taken."""
+    the kernel source or the launch settings have changed since the counters
+    were taken."""
     import hashlib
     try:
         vals = {}
@@ -47,6 +48,8 @@ def measured_traffic():
         with open(KERNEL_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
         if vals.get("kernel_source_sha256") != sha:
+            return None
+        if vals.get("launch") != json.dumps(launch or {}, sort_keys=True, separators=(",", ":")):
             return None
         return int(vals["fetch_bytes"]) + int(vals["write_bytes"])
     except (OSError, KeyError, ValueError):
@@ -167,7 +170,7 @@ def main():
     if args.profile_only:
         # a few launches of each kernel, plus a device-to-device copy of known
         # size whose counter readings calibrate FETCH_SIZE / WRITE_SIZE
-        for _ in range(3):
+        for _ in range(8):
             run(0, launch_of(dls, tuned))
         for _ in range(3):
             run(dls.DLS_PLAIN, launch_of(dls, {}))
@@ -409,7 +412,7 @@ def main():
                    "weighted_total": weighted, "parallelism": "single GPU",
                    "launch": tuned or "library defaults"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": measured_traffic(),
+                     "unit": "Tops/s", "frac": achieved / INT_PEAK_OPS, "traffic": measured_traffic(tuned),
                      "measured_peak": measured_peak / 1e12, "frac_of_measured": achieved / measured_peak},
         "cpu_baseline": cpu,
         "plain_kernel": {"value": leaves / (results["plain"]["ms_per_step"] * 1e-3),

@@ -189,7 +189,8 @@ typedef struct {
     int lds_masks;      /* persistent kernel: positive = keep the row and
                            column masks of each lane in LDS (one xor per
                            line to mark a value) instead of packed VGPR
-                           words; 0 / negative = VGPR layout (default)    */
+                           words; negative = VGPR layout; 0 = library
+                           default (LDS from order 9 on)                 */
 } dls_launch;
 
 /*

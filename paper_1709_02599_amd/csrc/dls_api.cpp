@@ -301,8 +301,10 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     a.stream = st;
     int block = (launch && launch->block) ? launch->block : 256;
     if (block < 64 || block > 1024 || block % 64) return DLS_EINVAL;
-    // line masks in LDS: off by default (the VGPR layout measured faster at N <= 8)
-    const bool lm = a.persistent && launch && launch->lds_masks > 0;
+    // line masks in LDS: by default from order 9 on, where the packed VGPR
+    // layout needs two words per kind (measured 21-27 % faster there); at
+    // N <= 8 the faster layout depends on the workload (autotuner)
+    const bool lm = a.persistent && ((launch && launch->lds_masks) ? launch->lds_masks > 0 : n >= 9);
     while (block > 64 && dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent, lm) > 64 * 1024) block /= 2;
     if (dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent, lm) > 64 * 1024) return DLS_EINVAL;
     a.tune.lds_masks = lm ? 1 : 0;
