@@ -123,6 +123,7 @@ struct Lane {
     uint32_t da;        // LDS address of the current level's descriptor (base + 4 * level)
     uint32_t da0;       // the same for the level at which this task began
     uint32_t sa;        // LDS address of this lane's stack entry for the current level
+    uint32_t sa0;       // the same for the level at which this task began
     uint32_t c32;       // squares completed since the last flush()
     uint64_t cnt;       // squares completed by this task (after flush())
 
@@ -159,15 +160,21 @@ struct Lane {
 
     __device__ __forceinline__ bool done() const { return cand == 0u && da == da0; }
 
-    // One DFS step; requires !done().  Level descriptors sit 4 bytes apart
-    // and this lane's stack entries `stride` bytes apart in LDS; da and sa
-    // track the current level's entries, so moving one level is an add.
-    // da_last = address of the last level's descriptor.
-    template <class S>
+    // One DFS step.  Level descriptors sit 4 bytes apart and this lane's
+    // stack entries `stride` bytes apart in LDS; da and sa track the current
+    // level's entries, so moving one level is an add.  da_last = address of
+    // the last level's descriptor.  PARK = false requires !done().  With
+    // PARK, a done lane may step too (see LdsLane::step): its up move is
+    // clamped at the start level.
+    template <class S, bool PARK = false>
     __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last) {
         const bool up = (cand == 0u);
-        const uint32_t nda = da + (up ? 0u - 4u : 4u);
-        const uint32_t nsa = sa + (up ? 0u - stride : stride);
+        uint32_t nda = da + (up ? 0u - 4u : 4u);
+        uint32_t nsa = sa + (up ? 0u - stride : stride);
+        if constexpr (PARK) {
+            nda = (uint32_t)max((int)nda, (int)da0);
+            nsa = (uint32_t)max((int)nsa, (int)sa0);
+        }
         const uint32_t ndesc = lds_ld<uint32_t>(nda);
         const uint32_t saved = lds_ld<S>(up ? nsa : sa);
         // up lanes write 0 into a slot nobody reads again
@@ -176,7 +183,7 @@ struct Lane {
         const uint32_t b = stored & (0u - stored);
         toggle(up ? ndesc : cur, b);
         const uint32_t nc = cands(ndesc);
-        const bool leaf = (nda == da_last);
+        const bool leaf = (nda == da_last) && !up;
         c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
         cand = up ? (stored ^ b) : (leaf ? 0u : nc);
         cur = ndesc;
@@ -201,12 +208,12 @@ struct Lane {
         if (lvl == kNone) {
             cand = 0u;
             da = da0 = dbase;
-            sa = lane_off;
+            sa = sa0 = lane_off;
             return;
         }
         cand = r.cl & 0xFFFFu;
         da = da0 = dbase + 4u * lvl;
-        sa = lane_off + lvl * stride;
+        sa = sa0 = lane_off + lvl * stride;
         cur = sdesc[lvl];
         if ((int)lvl == last) {
             c32 = (uint32_t)__builtin_popcount(cand);
@@ -258,6 +265,7 @@ struct LdsLane {
     uint32_t da;        // LDS address of the current level's descriptor (base + 16 * level)
     uint32_t da0;       // the same for the level at which this task began
     uint32_t sa;        // LDS address of this lane's stack entry for the current level
+    uint32_t sa0;       // the same for the level at which this task began
     uint32_t mbase;     // LDS address of this lane's row-0 mask word
     uint32_t c32;       // squares completed since the last flush()
     uint64_t cnt;       // squares completed by this task (after flush())
@@ -287,11 +295,21 @@ struct LdsLane {
         }
     }
 
+    // One DFS step, taken by every lane of the wave, busy or not.  A lane
+    // without work (its task finished, or none yet) sits at its start level
+    // with no candidates, and its up move is clamped there.  The first such
+    // step XORs the start slot's stale bit into the lane's own masks (the
+    // next task's from_rec() overwrites them) and writes 0 into that slot;
+    // from then on the step changes nothing.  So the search loop needs no
+    // per-lane test and no exec-mask merges.
+    // The new stack address follows from the new descriptor address:
+    // nsa = nda * kst + sc0 (kst = stride / 16, sc0 = stack address of
+    // level 0 minus dbase * kst, modulo 2^32).
     template <class S>
-    __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last) {
+    __device__ __forceinline__ void step(uint32_t kst, uint32_t sc0, uint32_t da_last) {
         const bool up = (cand == 0u);
-        const uint32_t nda = da + (up ? 0u - 16u : 16u);
-        const uint32_t nsa = sa + (up ? 0u - stride : stride);
+        const uint32_t nda = (uint32_t)max((int)(da + (up ? 0u - 16u : 16u)), (int)da0);
+        const uint32_t nsa = __umul24(nda, kst) + sc0;
         const uint4 nd = lds_ld4(nda);
         const uint4 td = lds_ld4(up ? nda : da);  // the cell whose value is marked or cleared
         const uint32_t saved = lds_ld<S>(up ? nsa : sa);
@@ -301,7 +319,7 @@ struct LdsLane {
         toggle_at(td, b, md, ad);
         const uint32_t r = lds_ld<uint32_t>(mbase + nd.x), c = lds_ld<uint32_t>(mbase + nd.y);
         const uint32_t nc = G::ALL & ~(r | c | (md & nd.z) | (ad & nd.w));
-        const bool leaf = (nda == da_last);
+        const bool leaf = (nda == da_last) && !up;
         c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
         cand = up ? (stored ^ b) : (leaf ? 0u : nc);
         da = nda;
@@ -327,12 +345,12 @@ struct LdsLane {
         if (lvl == kNone) {
             cand = 0u;
             da = da0 = dbase;
-            sa = lane_off;
+            sa = sa0 = lane_off;
             return;
         }
         cand = r.cl & 0xFFFFu;
         da = da0 = dbase + 16u * lvl;
-        sa = lane_off + lvl * stride;
+        sa = sa0 = lane_off + lvl * stride;
         if ((int)lvl == last) {
             c32 = (uint32_t)__builtin_popcount(cand);
             cand = 0u;
@@ -596,7 +614,7 @@ constexpr int kWaitVm1 = 0x0F71;
 constexpr int kWaitVm0 = 0x0F70;
 
 template <int N, bool VS, bool STATS, bool LM>
-__global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const Rec<N, VS> *recs, int64_t num,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) persistent_kernel(const Plan plan, const Rec<N, VS> *recs, int64_t num,
                                                           uint64_t *counts, uint32_t *status, uint64_t *steps,
                                                           Ctrl *ctrl, Rec<N, VS> *items, uint32_t *ready,
                                                           int64_t item_cap, Tuning tune, const Expand *ex) {
@@ -646,7 +664,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     LaneT L;
     L.cand = 0u;
     L.da = L.da0 = dbase;
-    L.sa = lane_off;
+    L.sa = L.sa0 = lane_off;
+    // LM stack address from descriptor address (see LdsLane::step)
+    const uint32_t kst = stride / 16u;
+    const uint32_t sc0 = lane_off - dbase * kst;
+    lds_st<S>(lane_off, (S)0);  // the parked start slot of a lane without a task
     L.cnt = 0;
     L.c32 = 0u;
     if constexpr (LM) L.mbase = dbase + kLmDescBytes + threadIdx.x * 4u;
@@ -654,9 +676,15 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
     bool has = false;           // lane holds a task (possibly finished)
     uint64_t *out = &ctrl->sink;  // where this lane's task count goes (a sink until the first task)
     // start the task of a record / give away part of this lane's task
+    // A parked lane's first step reads its start slot (see LdsLane::step).
+    // After a task that descended, that slot holds the single bit last taken
+    // there; a task that starts without candidates (dead, at the last level,
+    // or an empty record) would leave a stale value, so every start clears
+    // its slot (a task with candidates overwrites it on its first step).
     auto start = [&](const Rec<N, VS> &r) {
         if constexpr (LM) L.from_rec(r, dbase, last, lane_off, stride, lstride);
         else L.from_rec(r, sdesc, last, dbase, lane_off, stride);
+        lds_st<S>(L.sa0, (S)0);
     };
     auto give = [&](int lvl) -> Rec<N, VS> {
         if constexpr (LM) return L.donate(lvl, dbase, slot_of, (uint32_t)(out - counts), lstride);
@@ -676,10 +704,17 @@ __global__ void __launch_bounds__(1024) persistent_kernel(const Plan plan, const
 
     for (;;) {
         // ---------------- search ----------------
-        for (int it = 0; it < tune.refill_every; ++it) {
-            if (has && !L.done()) {
-                L.template step<S>(stride, da_last);
-                if (STATS) ++nsteps;
+        // every lane steps; idle lanes are parked at their start level.
+        // Two steps per trip (refill_every rounded up to even) let the
+        // register allocator alternate registers instead of copying them.
+        if (__ballot(has && !L.done())) {
+            for (int it = 0; it < tune.refill_every; it += 2) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (STATS) nsteps += (has && !L.done()) ? 1u : 0u;
+                    if constexpr (LM) L.template step<S>(kst, sc0, da_last);
+                    else L.template step<S, true>(stride, da_last);
+                }
             }
         }
         L.flush();
