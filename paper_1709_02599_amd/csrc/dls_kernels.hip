@@ -227,26 +227,32 @@ template <int N>
 using StackT = typename std::conditional<(N <= 8), uint8_t, uint16_t>::type;
 
 // LDS layout of the search kernels: level descriptors, then the stacks, then
-// (persistent kernel) one mailbox of 64 task records per wave
+// (persistent kernel, line masks in VGPRs) one mailbox of 64 task records per
+// wave for sharing work in the tail
 constexpr uint32_t kStackBase = sizeof(uint32_t) * kMaxLevels;
+#ifndef DLS_LM_PACK_MIN_N
+#define DLS_LM_PACK_MIN_N 9
+#endif
 
-__host__ __device__ inline uint32_t mailbox_offset(int nlev, int block, int elem) {
+__host__ __device__ inline uint32_t stacks_end(int nlev, int block, int elem) {
     const uint32_t end = kStackBase + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
     return (end + 15u) & ~15u;
 }
 
 // LDS layout with the line masks in LDS (LdsLane): a table of 16-byte level
-// descriptors, then the row and column masks (one 32-bit word per line and
-// lane, lines apart by `lstride` = 4 * block bytes, lanes side by side), then
-// the stacks, then the mailboxes.
-constexpr uint32_t kLmDescBytes = 16u * kMaxLevels;
+// descriptors (one per level of the plan), then the row and column masks (one
+// 32-bit word per line and lane, lines apart by `lstride` = 4 * block bytes,
+// lanes side by side), then the stacks.  LDS per lane
+// sets the occupancy of this layout, so nothing is sized for the maximum.
+__host__ __device__ inline uint32_t lm_desc_bytes(int nlev) { return 16u * (uint32_t)(nlev > 1 ? nlev : 1); }
 
-__host__ __device__ inline uint32_t lm_stack_base(int lines, int block) {
-    return kLmDescBytes + 4u * (uint32_t)lines * (uint32_t)block;
+__host__ __device__ inline uint32_t lm_stack_base(int lines, int nlev, int block) {
+    return lm_desc_bytes(nlev) + 4u * (uint32_t)lines * (uint32_t)block;
 }
 
-__host__ __device__ inline uint32_t lm_mailbox_offset(int lines, int nlev, int block, int elem) {
-    const uint32_t end = lm_stack_base(lines, block) + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
+__host__ __device__ inline uint32_t lm_stacks_end(int lines, int nlev, int block, int elem) {
+    const uint32_t end =
+        lm_stack_base(lines, nlev, block) + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
     return (end + 15u) & ~15u;
 }
 
@@ -259,7 +265,12 @@ __host__ __device__ inline uint32_t lm_mailbox_offset(int lines, int nlev, int b
 template <int N, bool VS>
 struct LdsLane {
     using G = Geo<N, VS>;
-    static constexpr int LINES = N + G::NCOL;
+    // PACK: LDS word k of a lane holds row k's mask in bits 0-15 and column
+    // k's mask in bits 16-31 (half the LDS, one shift more per toggle and
+    // read); otherwise one word per row, then one per column
+    static constexpr bool PACK = N >= DLS_LM_PACK_MIN_N;
+    static constexpr int LINES = PACK ? N : N + G::NCOL;
+    static constexpr uint32_t CSH = PACK ? 16u : 0u;  // column mask position in its word
     uint32_t md, ad;    // diagonal masks
     uint32_t cand;      // remaining candidates at the current level
     uint32_t da;        // LDS address of the current level's descriptor (base + 16 * level)
@@ -284,12 +295,12 @@ struct LdsLane {
         if constexpr (VS) {
             const uint32_t rb = (1u << (N - 1)) >> (__builtin_ctz(b) & 31u);  // N-1-v
             lds_xor(mbase + t.x, b | rb);
-            lds_xor(mbase + t.y, b);
+            lds_xor(mbase + t.y, b << CSH);
             dmd ^= (b & t.z) | (rb & t.w);
             dad ^= (b & t.w) | (rb & t.z);
         } else {
             lds_xor(mbase + t.x, b);
-            lds_xor(mbase + t.y, b);
+            lds_xor(mbase + t.y, b << CSH);
             dmd ^= b & t.z;
             dad ^= b & t.w;
         }
@@ -317,7 +328,8 @@ struct LdsLane {
         const uint32_t stored = up ? saved : cand;
         const uint32_t b = stored & (0u - stored);
         toggle_at(td, b, md, ad);
-        const uint32_t r = lds_ld<uint32_t>(mbase + nd.x), c = lds_ld<uint32_t>(mbase + nd.y);
+        // PACK: the row word's upper half (a column mask) falls outside ALL
+        const uint32_t r = lds_ld<uint32_t>(mbase + nd.x), c = lds_ld<uint32_t>(mbase + nd.y) >> CSH;
         const uint32_t nc = G::ALL & ~(r | c | (md & nd.z) | (ad & nd.w));
         const bool leaf = (nda == da_last) && !up;
         c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
@@ -330,13 +342,17 @@ struct LdsLane {
     __device__ __forceinline__ void from_rec(const Rec<N, VS> &r, uint32_t dbase, int last, uint32_t lane_off,
                                              uint32_t stride, uint32_t lstride) {
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            lds_st<uint32_t>(mbase + (uint32_t)i * lstride,
-                             (uint32_t)(r.R[i / G::LPW] >> ((i % G::LPW) * N)) & G::ALL);
+        for (int i = 0; i < N; ++i) {
+            uint32_t w = (uint32_t)(r.R[i / G::LPW] >> ((i % G::LPW) * N)) & G::ALL;
+            if (PACK && i < G::NCOL) w |= ((uint32_t)(r.C[i / G::LPW] >> ((i % G::LPW) * N)) & G::ALL) << 16;
+            lds_st<uint32_t>(mbase + (uint32_t)i * lstride, w);
+        }
+        if constexpr (!PACK) {
 #pragma unroll
-        for (int j = 0; j < G::NCOL; ++j)
-            lds_st<uint32_t>(mbase + (uint32_t)(N + j) * lstride,
-                             (uint32_t)(r.C[j / G::LPW] >> ((j % G::LPW) * N)) & G::ALL);
+            for (int j = 0; j < G::NCOL; ++j)
+                lds_st<uint32_t>(mbase + (uint32_t)(N + j) * lstride,
+                                 (uint32_t)(r.C[j / G::LPW] >> ((j % G::LPW) * N)) & G::ALL);
+        }
         md = r.diag & 0xFFFFu;
         ad = r.diag >> 16;
         cnt = 0;
@@ -374,11 +390,17 @@ struct LdsLane {
 #pragma unroll
         for (int k = 0; k < G::WC; ++k) r.C[k] = 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            r.R[i / G::LPW] |= (uint64_t)lds_ld<uint32_t>(mbase + (uint32_t)i * lstride) << ((i % G::LPW) * N);
+        for (int i = 0; i < N; ++i) {
+            const uint32_t w = lds_ld<uint32_t>(mbase + (uint32_t)i * lstride);
+            r.R[i / G::LPW] |= (uint64_t)(w & 0xFFFFu) << ((i % G::LPW) * N);
+            if (PACK && i < G::NCOL) r.C[i / G::LPW] |= (uint64_t)(w >> 16) << ((i % G::LPW) * N);
+        }
+        if constexpr (!PACK) {
 #pragma unroll
-        for (int j = 0; j < G::NCOL; ++j)
-            r.C[j / G::LPW] |= (uint64_t)lds_ld<uint32_t>(mbase + (uint32_t)(N + j) * lstride) << ((j % G::LPW) * N);
+            for (int j = 0; j < G::NCOL; ++j)
+                r.C[j / G::LPW] |= (uint64_t)lds_ld<uint32_t>(mbase + (uint32_t)(N + j) * lstride)
+                                   << ((j % G::LPW) * N);
+        }
         uint32_t rmd = tmd, rad = tad;
         for (int l = lvl; l < dep; ++l) {  // replay: this lane keeps its branch
             const uint32_t sv = *slot_of(l);
@@ -404,7 +426,7 @@ __device__ __forceinline__ void lm_build_desc(const Plan &plan, unsigned char *s
         const uint32_t d = plan.desc[k];
         const uint32_t i = ((d >> 6) & 3u) * G::LPW + (d & 63u) / N;
         const uint32_t j = ((d >> 14) & 3u) * G::LPW + ((d >> 8) & 63u) / N;
-        t[k] = make_uint4(i * lstride, (N + j) * lstride, d_md(d), d_ad(d));
+        t[k] = make_uint4(i * lstride, (LdsLane<N, VS>::PACK ? j : N + j) * lstride, d_md(d), d_ad(d));
     }
 }
 
@@ -572,6 +594,30 @@ __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// lane index of the set bit of rank k in mask (k < popcount(mask)): the
+// largest p with popcount(mask below p) <= k, by binary search
+__device__ __forceinline__ int kth_lane(uint64_t mask, uint32_t k) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int p = pos + w;
+        if ((uint32_t)__popcll(mask & ((1ull << p) - 1ull)) <= k) pos = p;
+    }
+    return pos;
+}
+
+// value of v in lane src, word by word (every lane of the wave must take part)
+template <class T>
+__device__ __forceinline__ T shfl_words(const T &v, int src) {
+    static_assert(sizeof(T) % 4 == 0, "shuffled in 32-bit words");
+    T out;
+    const uint32_t *a = reinterpret_cast<const uint32_t *>(&v);
+    uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) o[k] = (uint32_t)__shfl((int)a[k], src, 64);
+    return out;
+}
+
 __device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
@@ -621,7 +667,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     using S = StackT<N>;
     // LM: line masks in LDS (LdsLane), else in VGPRs (Lane)
     using LaneT = typename std::conditional<LM, LdsLane<N, VS>, Lane<N, VS>>::type;
-    constexpr int LINES = N + Geo<N, VS>::NCOL;
+    constexpr int LINES = LdsLane<N, VS>::LINES;
     if (ex) {
         // the batch as the expansion passes left it
         recs = reinterpret_cast<const Rec<N, VS> *>(ex->recs);
@@ -643,7 +689,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     const bool poller = (threadIdx.x >> 6) == 0;  // one wave per workgroup waits for donations
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t dbase = lds_of(smem);
-    const uint32_t sbase = LM ? lm_stack_base(LINES, blockDim.x) : kStackBase;
+    const uint32_t sbase = LM ? lm_stack_base(LINES, nlev, blockDim.x) : kStackBase;
     const uint32_t loff = sbase + threadIdx.x * (uint32_t)sizeof(S);  // from smem
     const uint32_t lane_off = dbase + loff;                             // LDS address
     const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
@@ -671,7 +717,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     lds_st<S>(lane_off, (S)0);  // the parked start slot of a lane without a task
     L.cnt = 0;
     L.c32 = 0u;
-    if constexpr (LM) L.mbase = dbase + kLmDescBytes + threadIdx.x * 4u;
+    if constexpr (LM) L.mbase = dbase + lm_desc_bytes(nlev) + threadIdx.x * 4u;
     const uint32_t da_last = dbase + (LM ? 16u : 4u) * (uint32_t)last;
     bool has = false;           // lane holds a task (possibly finished)
     uint64_t *out = &ctrl->sink;  // where this lane's task count goes (a sink until the first task)
@@ -697,10 +743,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     uint64_t seen_sig = ~0ull, seen_at = 0;
     uint32_t backoff = 1, tick = 0;
     bool asked = false;         // this (idle poller) wave is counted in ctrl->hungry
-    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(
-                           smem + (LM ? lm_mailbox_offset(LINES, nlev, blockDim.x, sizeof(S))
-                                      : mailbox_offset(nlev, blockDim.x, sizeof(S)))) +
-                       (threadIdx.x & ~63u);
 
     for (;;) {
         // ---------------- search ----------------
@@ -786,9 +828,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             stored = 0;
         }
         want = __ballot(!has);
-        // ---------------- share work inside the wave (LDS mailbox) ----------------
+        // ---------------- share work inside the wave ----------------
         // busy lanes hand the untried siblings at their shallowest open level
-        // to idle lanes of the same wave, as task records
+        // to idle lanes of the same wave, as task records (any number per
+        // round)
         if (want && want != ~0ull) {
             int lvl = -1;
             if (has && !L.done()) {
@@ -808,20 +851,31 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             if (m) {
                 const uint64_t drank = (uint64_t)__popcll(donors & below);
                 const uint64_t rrank = (uint64_t)__popcll(want & below);
-                if (lvl >= 0 && drank < m) {
-                    const Rec<N, VS> r = give(lvl);
-                    mbox[drank] = r;
+                // the idle lane of rank k takes the record of the donor of rank k
+                const bool take = !has && rrank < m;
+                Rec<N, VS> got;
+                if constexpr (LM) {
+                    // through registers: LDS sets this layout's occupancy
+                    Rec<N, VS> r{};
+                    if (lvl >= 0 && drank < m) r = give(lvl);
+                    const int src = take ? kth_lane(donors, (uint32_t)rrank) : lane;
+                    got = shfl_words(r, src);
+                } else {
+                    // through the wave's LDS mailbox (cheaper in registers)
+                    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(smem + stacks_end(nlev, blockDim.x, sizeof(S))) +
+                                       (threadIdx.x & ~63u);
+                    if (lvl >= 0 && drank < m) mbox[drank] = give(lvl);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    if (take) got = mbox[rrank];
+                    __builtin_amdgcn_wave_barrier();
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                if (!has && rrank < m) {
-                    const Rec<N, VS> r = mbox[rrank];
-                    start(r);
-                    out = &counts[r.origin];
+                if (take) {
+                    start(got);
+                    out = &counts[got.origin];
                     stored = 0;
                     has = true;
                 }
-                __builtin_amdgcn_wave_barrier();
                 want = __ballot(!has);
             }
         }
@@ -1546,10 +1600,10 @@ size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent, bool lds_
     const int elem = n <= 8 ? 1 : 2;
     if (!persistent) return kStackBase + (size_t)elem * (size_t)(nlev > 1 ? nlev : 1) * block;
     if (lds_masks) {
-        const int lines = n + (vs ? (n + 1) / 2 : n);
-        return lm_mailbox_offset(lines, nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
+        const int lines = n >= DLS_LM_PACK_MIN_N ? n : n + (vs ? (n + 1) / 2 : n);  // LdsLane<n, vs>::LINES
+        return lm_stacks_end(lines, nlev, block, elem);
     }
-    return mailbox_offset(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
+    return stacks_end(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
 }
 
 hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream) {
