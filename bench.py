@@ -63,8 +63,8 @@ OPS_PER_DOWN_STEP = 12
 OPS_PER_TASK = 3
 
 
-LAUNCH_FIELDS = ("block", "refill_every", "order_variant", "expand_target", "chunk_min", "steal_depth",
-                 "lds_masks")
+LAUNCH_FIELDS = ("block", "blocks_per_cu", "refill_every", "order_variant", "expand_target", "chunk_min",
+                 "steal_depth", "lds_masks")
 
 
 def tuned_launch(n, flags, workload):
@@ -82,7 +82,7 @@ def tuned_launch(n, flags, workload):
 
 def launch_of(dls, settings, time_kernel=0):
     kw = {k: int(settings.get(k, 0)) for k in LAUNCH_FIELDS}
-    return dls.DlsLaunch(blocks_per_cu=0, time_kernel=time_kernel, **kw)
+    return dls.DlsLaunch(time_kernel=time_kernel, **kw)
 
 
 def parse():

@@ -191,13 +191,22 @@ def main(argv=None):
 
     if want("order8-symbreak-row1"):
         pre, mult = dls_split(8, DLS_SYMBREAK, 26)
+        # stage 1: fill order, workgroup, refill cadence, mask layout
         r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
-                 space={"order_variant": VARIANTS, "block": BLOCKS, "refill_every": REFILLS, "lds_masks": (0, 1)},
-                 default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": 0})
+                 space={"order_variant": VARIANTS, "block": BLOCKS, "refill_every": REFILLS, "lds_masks": (-1, 1)},
+                 default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1}, save=False)
+        first = {k: v for k, v in r["best"].items() if k != "ms"}
+        # stage 2: grid size (1x, 1.5x, 2x the resident default; waves beyond
+        # the resident ones only shrink the guided chunks) and smallest chunk
+        d = 2048 // first["block"]
+        r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
+                 space={**{k: (v,) for k, v in first.items()}, "blocks_per_cu": (0, d * 3 // 2, d * 2),
+                        "chunk_min": (0, 2, 4, 16)},
+                 default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1})
         print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
                           "plain_ms": r["plain_ms"]}), flush=True)
         d = tune_depth(8, DLS_SYMBREAK, (20, 22, 24, 26, 27, 28), "order8-symbreak",
-                       launch={k: r["best"][k] for k in ("block", "refill_every", "order_variant", "lds_masks")},
+                       launch={k: v for k, v in r["best"].items() if k != "ms"},
                        reps=args.reps)
         print(json.dumps({"workload": "order8-symbreak", "depths": d["table"]}), flush=True)
     if want("order7-diag11"):
