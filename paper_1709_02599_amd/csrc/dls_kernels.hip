@@ -165,15 +165,18 @@ struct Lane {
     // level's entries, so moving one level is an add.  da_last = address of
     // the last level's descriptor.  PARK = false requires !done().  With
     // PARK, a done lane may step too (see LdsLane::step): its up move is
-    // clamped at the start level.
+    // clamped at the start level, and the stack address follows from the
+    // descriptor address as nda * kst + sc0 (kst = stride / 4).
     template <class S, bool PARK = false>
-    __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last) {
+    __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last, uint32_t kst = 0u, uint32_t sc0 = 0u) {
         const bool up = (cand == 0u);
         uint32_t nda = da + (up ? 0u - 4u : 4u);
-        uint32_t nsa = sa + (up ? 0u - stride : stride);
+        uint32_t nsa;
         if constexpr (PARK) {
             nda = (uint32_t)max((int)nda, (int)da0);
-            nsa = (uint32_t)max((int)nsa, (int)sa0);
+            nsa = __umul24(nda, kst) + sc0;
+        } else {
+            nsa = sa + (up ? 0u - stride : stride);
         }
         const uint32_t ndesc = lds_ld<uint32_t>(nda);
         const uint32_t saved = lds_ld<S>(up ? nsa : sa);
@@ -711,8 +714,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     L.cand = 0u;
     L.da = L.da0 = dbase;
     L.sa = L.sa0 = lane_off;
-    // LM stack address from descriptor address (see LdsLane::step)
-    const uint32_t kst = stride / 16u;
+    // stack address from descriptor address (see Lane::step, LdsLane::step)
+    const uint32_t kst = stride / (LM ? 16u : 4u);
     const uint32_t sc0 = lane_off - dbase * kst;
     lds_st<S>(lane_off, (S)0);  // the parked start slot of a lane without a task
     L.cnt = 0;
@@ -755,7 +758,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                 for (int u = 0; u < 2; ++u) {
                     if (STATS) nsteps += (has && !L.done()) ? 1u : 0u;
                     if constexpr (LM) L.template step<S>(kst, sc0, da_last);
-                    else L.template step<S, true>(stride, da_last);
+                    else L.template step<S, true>(stride, da_last, kst, sc0);
                 }
             }
         }
