@@ -91,6 +91,12 @@ template <class T>
 __device__ __forceinline__ void lds_st(uint32_t a, T v) {
     *reinterpret_cast<__attribute__((address_space(3))) T *>((uintptr_t)a) = v;
 }
+// 8-byte LDS load (one ds_read_b64)
+__device__ __forceinline__ uint2 lds_ld2(uint32_t a) {
+    typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+    const v2u v = *reinterpret_cast<const __attribute__((address_space(3))) v2u *>((uintptr_t)a);
+    return make_uint2(v.x, v.y);
+}
 // 16-byte LDS load (one ds_read_b128)
 __device__ __forceinline__ uint4 lds_ld4(uint32_t a) {
     typedef uint32_t v4u __attribute__((ext_vector_type(4)));
@@ -123,7 +129,6 @@ struct Lane {
     uint32_t da;        // LDS address of the current level's descriptor (base + 4 * level)
     uint32_t da0;       // the same for the level at which this task began
     uint32_t sa;        // LDS address of this lane's stack entry for the current level
-    uint32_t sa0;       // the same for the level at which this task began
     uint32_t c32;       // squares completed since the last flush()
     uint64_t cnt;       // squares completed by this task (after flush())
 
@@ -163,21 +168,12 @@ struct Lane {
     // One DFS step.  Level descriptors sit 4 bytes apart and this lane's
     // stack entries `stride` bytes apart in LDS; da and sa track the current
     // level's entries, so moving one level is an add.  da_last = address of
-    // the last level's descriptor.  PARK = false requires !done().  With
-    // PARK, a done lane may step too (see LdsLane::step): its up move is
-    // clamped at the start level, and the stack address follows from the
-    // descriptor address as nda * kst + sc0 (kst = stride / 4).
-    template <class S, bool PARK = false>
-    __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last, uint32_t kst = 0u, uint32_t sc0 = 0u) {
+    // the last level's descriptor.  Requires !done().
+    template <class S>
+    __device__ __forceinline__ void step(uint32_t stride, uint32_t da_last) {
         const bool up = (cand == 0u);
-        uint32_t nda = da + (up ? 0u - 4u : 4u);
-        uint32_t nsa;
-        if constexpr (PARK) {
-            nda = (uint32_t)max((int)nda, (int)da0);
-            nsa = __umul24(nda, kst) + sc0;
-        } else {
-            nsa = sa + (up ? 0u - stride : stride);
-        }
+        const uint32_t nda = da + (up ? 0u - 4u : 4u);
+        const uint32_t nsa = sa + (up ? 0u - stride : stride);
         const uint32_t ndesc = lds_ld<uint32_t>(nda);
         const uint32_t saved = lds_ld<S>(up ? nsa : sa);
         // up lanes write 0 into a slot nobody reads again
@@ -186,7 +182,7 @@ struct Lane {
         const uint32_t b = stored & (0u - stored);
         toggle(up ? ndesc : cur, b);
         const uint32_t nc = cands(ndesc);
-        const bool leaf = (nda == da_last) && !up;
+        const bool leaf = (nda == da_last);
         c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
         cand = up ? (stored ^ b) : (leaf ? 0u : nc);
         cur = ndesc;
@@ -211,12 +207,12 @@ struct Lane {
         if (lvl == kNone) {
             cand = 0u;
             da = da0 = dbase;
-            sa = sa0 = lane_off;
+            sa = lane_off;
             return;
         }
         cand = r.cl & 0xFFFFu;
         da = da0 = dbase + 4u * lvl;
-        sa = sa0 = lane_off + lvl * stride;
+        sa = lane_off + lvl * stride;
         cur = sdesc[lvl];
         if ((int)lvl == last) {
             c32 = (uint32_t)__builtin_popcount(cand);
@@ -279,7 +275,6 @@ struct LdsLane {
     uint32_t da;        // LDS address of the current level's descriptor (base + 16 * level)
     uint32_t da0;       // the same for the level at which this task began
     uint32_t sa;        // LDS address of this lane's stack entry for the current level
-    uint32_t sa0;       // the same for the level at which this task began
     uint32_t mbase;     // LDS address of this lane's row-0 mask word
     uint32_t c32;       // squares completed since the last flush()
     uint64_t cnt;       // squares completed by this task (after flush())
@@ -364,12 +359,12 @@ struct LdsLane {
         if (lvl == kNone) {
             cand = 0u;
             da = da0 = dbase;
-            sa = sa0 = lane_off;
+            sa = lane_off;
             return;
         }
         cand = r.cl & 0xFFFFu;
         da = da0 = dbase + 16u * lvl;
-        sa = sa0 = lane_off + lvl * stride;
+        sa = lane_off + lvl * stride;
         if ((int)lvl == last) {
             c32 = (uint32_t)__builtin_popcount(cand);
             cand = 0u;
@@ -419,6 +414,157 @@ struct LdsLane {
         return r;
     }
 };
+
+// Lane state of the persistent kernel with the line masks in VGPRs (packed
+// 64-bit words as in Lane) and 8-byte level descriptors in LDS:
+//   x = row shift | row word << 6 | (on main diagonal ? ALL << 16 : 0)
+//   y = column shift | column word << 6 | (on antidiagonal ? ALL << 16 : 0)
+// The 64-bit shifts read only the low 6 bits of x / y, and the diagonal
+// masks are kept in bits 16-31 (mdh, adh), so a diagonal test is one AND
+// with x or y: no field extraction in the search loop.
+constexpr uint32_t kVlStackBase = 8u * kMaxLevels;
+
+__host__ __device__ inline uint32_t vl_stacks_end(int nlev, int block, int elem) {
+    const uint32_t end = kVlStackBase + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
+    return (end + 15u) & ~15u;
+}
+
+template <int N, bool VS>
+struct VLane {
+    using G = Geo<N, VS>;
+    uint64_t R[G::WR];  // row lines
+    uint64_t C[G::WC];  // column lines (left half only with VS)
+    uint32_t mdh, adh;  // diagonal masks << 16
+    uint32_t cand;      // remaining candidates at the current level
+    uint2 cur;          // descriptor of the current level's cell
+    uint32_t da;        // LDS address of the current level's descriptor (base + 8 * level)
+    uint32_t da0;       // the same for the level at which this task began
+    uint32_t sa;        // LDS address of this lane's stack entry for the current level
+    uint32_t c32;       // squares completed since the last flush()
+    uint64_t cnt;       // squares completed by this task (after flush())
+
+    __device__ __forceinline__ int depth(uint32_t dbase) const { return (int)((da - dbase) >> 3); }
+    __device__ __forceinline__ int start_level(uint32_t dbase) const { return (int)((da0 - dbase) >> 3); }
+    __device__ __forceinline__ void flush() {
+        cnt += c32;
+        c32 = 0u;
+    }
+    __device__ __forceinline__ bool done() const { return cand == 0u && da == da0; }
+
+    __device__ __forceinline__ uint32_t cands(const uint2 &d) const {
+        const uint32_t r = (uint32_t)(pickw<G::WR>(R, (d.x >> 6) & 3u) >> (d.x & 63u));
+        const uint32_t c = (uint32_t)(pickw<G::WC>(C, (d.y >> 6) & 3u) >> (d.y & 63u));
+        return G::ALL & ~(r | c | (((mdh & d.x) | (adh & d.y)) >> 16));
+    }
+
+    // mark or clear (XOR) the value bit b at the cell of descriptor d
+    __device__ __forceinline__ void toggle(const uint2 &d, uint32_t b) {
+        const uint32_t bh = b << 16;
+        if constexpr (VS) {
+            const uint32_t rb = (1u << (N - 1)) >> (__builtin_ctz(b) & 31u);  // N-1-v
+            const uint32_t rbh = rb << 16;
+            flipw<G::WR>(R, (d.x >> 6) & 3u, (uint64_t)(b | rb) << (d.x & 63u));
+            flipw<G::WC>(C, (d.y >> 6) & 3u, (uint64_t)b << (d.y & 63u));
+            mdh ^= (bh & d.x) | (rbh & d.y);
+            adh ^= (bh & d.y) | (rbh & d.x);
+        } else {
+            flipw<G::WR>(R, (d.x >> 6) & 3u, (uint64_t)b << (d.x & 63u));
+            flipw<G::WC>(C, (d.y >> 6) & 3u, (uint64_t)b << (d.y & 63u));
+            mdh ^= bh & d.x;
+            adh ^= bh & d.y;
+        }
+    }
+
+    // One DFS step, taken by every lane of the wave (see LdsLane::step for
+    // the parked lanes).  nsa = nda * kst + sc0 (kst = stride / 8).
+    template <class S>
+    __device__ __forceinline__ void step(uint32_t kst, uint32_t sc0, uint32_t da_last) {
+        const bool up = (cand == 0u);
+        const uint32_t nda = (uint32_t)max((int)(da + (up ? 0u - 8u : 8u)), (int)da0);
+        const uint32_t nsa = __umul24(nda, kst) + sc0;
+        const uint2 nd = lds_ld2(nda);
+        const uint32_t saved = lds_ld<S>(up ? nsa : sa);
+        lds_st<S>(sa, (S)cand);  // up lanes write 0 into a slot nobody reads again
+        const uint32_t stored = up ? saved : cand;
+        const uint32_t b = stored & (0u - stored);
+        toggle(up ? nd : cur, b);
+        const uint32_t nc = cands(nd);
+        const bool leaf = (nda == da_last) && !up;
+        c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
+        cand = up ? (stored ^ b) : (leaf ? 0u : nc);
+        cur = nd;
+        da = nda;
+        sa = nsa;
+    }
+
+    // Start the task of record r (dbase: LDS address of the 8-byte
+    // descriptor table; lane_off / stride: this lane's level-0 stack entry
+    // and the distance between levels).
+    __device__ __forceinline__ void from_rec(const Rec<N, VS> &r, uint32_t dbase, int last, uint32_t lane_off,
+                                             uint32_t stride) {
+#pragma unroll
+        for (int k = 0; k < G::WR; ++k) R[k] = r.R[k];
+#pragma unroll
+        for (int k = 0; k < G::WC; ++k) C[k] = r.C[k];
+        mdh = r.diag << 16;
+        adh = r.diag & 0xFFFF0000u;
+        cnt = 0;
+        c32 = 0u;
+        const uint32_t lvl = r.cl >> 16;
+        if (lvl == kNone) {
+            cand = 0u;
+            da = da0 = dbase;
+            sa = lane_off;
+            cur = lds_ld2(dbase);
+            return;
+        }
+        cand = r.cl & 0xFFFFu;
+        da = da0 = dbase + 8u * lvl;
+        sa = lane_off + lvl * stride;
+        cur = lds_ld2(da);
+        if ((int)lvl == last) {
+            c32 = (uint32_t)__builtin_popcount(cand);
+            cand = 0u;
+        }
+    }
+
+    // Give away the untried siblings at level lvl: the record holds the
+    // masks as they were on entering lvl (the values taken at levels
+    // lvl..depth-1 cleared again) and the candidates not yet tried there;
+    // the lane keeps only the branch in progress.
+    template <class SlotOf>
+    __device__ __forceinline__ Rec<N, VS> donate(int lvl, uint32_t dbase, SlotOf slot_of, uint32_t origin) const {
+        VLane T = *this;
+        for (int l = depth(dbase) - 1; l >= lvl; --l) {
+            const uint32_t sv = *slot_of(l);
+            T.toggle(lds_ld2(dbase + 8u * (uint32_t)l), sv & (0u - sv));
+        }
+        const uint32_t sv = *slot_of(lvl);
+        const uint32_t b = sv & (0u - sv);
+        Rec<N, VS> r;
+#pragma unroll
+        for (int k = 0; k < G::WR; ++k) r.R[k] = T.R[k];
+#pragma unroll
+        for (int k = 0; k < G::WC; ++k) r.C[k] = T.C[k];
+        r.diag = (T.mdh >> 16) | (T.adh & 0xFFFF0000u);
+        r.cl = (sv ^ b) | ((uint32_t)lvl << 16);
+        r.origin = origin;
+        r.pad = 0;
+        *slot_of(lvl) = (decltype(*slot_of(lvl) + 0))b;
+        return r;
+    }
+};
+
+// 8-byte descriptor table of VLane from the plan
+template <int N, bool VS>
+__device__ __forceinline__ void vl_build_desc(const Plan &plan, unsigned char *smem) {
+    using G = Geo<N, VS>;
+    uint2 *t = reinterpret_cast<uint2 *>(smem);
+    for (int k = threadIdx.x; k < plan.nlev; k += blockDim.x) {
+        const uint32_t d = plan.desc[k];
+        t[k] = make_uint2((d & 0xFFu) | ((d_md(d) & G::ALL) << 16), ((d >> 8) & 0xFFu) | ((d_ad(d) & G::ALL) << 16));
+    }
+}
 
 // descriptor table of the LDS-mask layout from the plan (one entry per level)
 template <int N, bool VS>
@@ -630,33 +776,6 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
 // s_memrealtime ticks at 100 MHz: 20 s without any queue progress ends the kernel
 constexpr uint64_t kStallTicks = 100000000ull * 20;
 
-// Give away the untried siblings at level lvl of a lane's search: the record
-// holds the masks as they were on entering lvl (the values taken at levels
-// lvl..d-1 cleared again) and the candidates not yet tried there; the lane
-// keeps only the branch in progress.
-template <int N, bool VS, class SlotOf>
-__device__ __forceinline__ Rec<N, VS> donate(const Lane<N, VS> &L, int lvl, const uint32_t *sdesc, SlotOf slot_of,
-                                             uint32_t origin, uint32_t dbase) {
-    Lane<N, VS> T = L;
-    for (int l = L.depth(dbase) - 1; l >= lvl; --l) {
-        const uint32_t sv = *slot_of(l);
-        T.toggle(sdesc[l], sv & (0u - sv));
-    }
-    const uint32_t sv = *slot_of(lvl);
-    const uint32_t b = sv & (0u - sv);
-    Rec<N, VS> r;
-#pragma unroll
-    for (int k = 0; k < Geo<N, VS>::WR; ++k) r.R[k] = T.R[k];
-#pragma unroll
-    for (int k = 0; k < Geo<N, VS>::WC; ++k) r.C[k] = T.C[k];
-    r.diag = T.md | (T.ad << 16);
-    r.cl = (sv ^ b) | ((uint32_t)lvl << 16);
-    r.origin = origin;
-    r.pad = 0;
-    *slot_of(lvl) = (decltype(*slot_of(lvl) + 0))b;
-    return r;
-}
-
 // s_waitcnt immediate for gfx9: vmcnt <= 1 (bits 3:0 and 15:14), no wait on
 // expcnt (bits 6:4 = 7) or lgkmcnt (bits 11:8 = 15)
 constexpr int kWaitVm1 = 0x0F71;
@@ -669,7 +788,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                                                           int64_t item_cap, Tuning tune, const Expand *ex) {
     using S = StackT<N>;
     // LM: line masks in LDS (LdsLane), else in VGPRs (Lane)
-    using LaneT = typename std::conditional<LM, LdsLane<N, VS>, Lane<N, VS>>::type;
+    using LaneT = typename std::conditional<LM, LdsLane<N, VS>, VLane<N, VS>>::type;
     constexpr int LINES = LdsLane<N, VS>::LINES;
     if (ex) {
         // the batch as the expansion passes left it
@@ -678,21 +797,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
         counts = ex->counts;
     }
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *sdesc = reinterpret_cast<uint32_t *>(smem);
     const int nlev = plan.nlev;
     const uint32_t lstride = blockDim.x * 4u;  // LM: bytes between two lines' mask words
-    if constexpr (LM) {
-        lm_build_desc<N, VS>(plan, smem, lstride);
-    } else {
-        for (int k = threadIdx.x; k < nlev; k += blockDim.x) sdesc[k] = plan.desc[k];
-    }
+    if constexpr (LM) lm_build_desc<N, VS>(plan, smem, lstride);
+    else vl_build_desc<N, VS>(plan, smem);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const bool poller = (threadIdx.x >> 6) == 0;  // one wave per workgroup waits for donations
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t dbase = lds_of(smem);
-    const uint32_t sbase = LM ? lm_stack_base(LINES, nlev, blockDim.x) : kStackBase;
+    const uint32_t sbase = LM ? lm_stack_base(LINES, nlev, blockDim.x) : kVlStackBase;
     const uint32_t loff = sbase + threadIdx.x * (uint32_t)sizeof(S);  // from smem
     const uint32_t lane_off = dbase + loff;                             // LDS address
     const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
@@ -713,15 +828,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     LaneT L;
     L.cand = 0u;
     L.da = L.da0 = dbase;
-    L.sa = L.sa0 = lane_off;
-    // stack address from descriptor address (see Lane::step, LdsLane::step)
-    const uint32_t kst = stride / (LM ? 16u : 4u);
+    L.sa = lane_off;
+    if constexpr (!LM) L.cur = make_uint2(0u, 0u);
+    // stack address from descriptor address (see VLane::step, LdsLane::step)
+    constexpr uint32_t kDescBytes = LM ? 16u : 8u;
+    const uint32_t kst = stride / kDescBytes;
     const uint32_t sc0 = lane_off - dbase * kst;
     lds_st<S>(lane_off, (S)0);  // the parked start slot of a lane without a task
     L.cnt = 0;
     L.c32 = 0u;
     if constexpr (LM) L.mbase = dbase + lm_desc_bytes(nlev) + threadIdx.x * 4u;
-    const uint32_t da_last = dbase + (LM ? 16u : 4u) * (uint32_t)last;
+    const uint32_t da_last = dbase + kDescBytes * (uint32_t)last;
     bool has = false;           // lane holds a task (possibly finished)
     uint64_t *out = &ctrl->sink;  // where this lane's task count goes (a sink until the first task)
     // start the task of a record / give away part of this lane's task
@@ -732,12 +849,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     // its slot (a task with candidates overwrites it on its first step).
     auto start = [&](const Rec<N, VS> &r) {
         if constexpr (LM) L.from_rec(r, dbase, last, lane_off, stride, lstride);
-        else L.from_rec(r, sdesc, last, dbase, lane_off, stride);
-        lds_st<S>(L.sa0, (S)0);
+        else L.from_rec(r, dbase, last, lane_off, stride);
+        lds_st<S>(L.sa, (S)0);
     };
     auto give = [&](int lvl) -> Rec<N, VS> {
         if constexpr (LM) return L.donate(lvl, dbase, slot_of, (uint32_t)(out - counts), lstride);
-        else return donate(L, lvl, sdesc, slot_of, (uint32_t)(out - counts), dbase);
+        else return L.donate(lvl, dbase, slot_of, (uint32_t)(out - counts));
     };
     uint64_t stored = 0;        // part of L.cnt already in *out
     bool static_left = true;    // wave-uniform
@@ -757,8 +874,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     if (STATS) nsteps += (has && !L.done()) ? 1u : 0u;
-                    if constexpr (LM) L.template step<S>(kst, sc0, da_last);
-                    else L.template step<S, true>(stride, da_last, kst, sc0);
+                    L.template step<S>(kst, sc0, da_last);
                 }
             }
         }
@@ -865,7 +981,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                     got = shfl_words(r, src);
                 } else {
                     // through the wave's LDS mailbox (cheaper in registers)
-                    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(smem + stacks_end(nlev, blockDim.x, sizeof(S))) +
+                    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(smem + vl_stacks_end(nlev, blockDim.x, sizeof(S))) +
                                        (threadIdx.x & ~63u);
                     if (lvl >= 0 && drank < m) mbox[drank] = give(lvl);
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -1606,7 +1722,7 @@ size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent, bool lds_
         const int lines = n >= DLS_LM_PACK_MIN_N ? n : n + (vs ? (n + 1) / 2 : n);  // LdsLane<n, vs>::LINES
         return lm_stacks_end(lines, nlev, block, elem);
     }
-    return stacks_end(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
+    return vl_stacks_end(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
 }
 
 hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream) {
