@@ -276,14 +276,16 @@ def main():
         spat = (spre[0] != 0xFF).astype(np.uint8)
         sd_pre = torch.from_numpy(spre).to(dev)
         sd_cnt = torch.zeros(len(spre), dtype=torch.int64, device=dev)
-        sustained = {"prefixes": len(spre), "leaves": ORDER8_FIXED}
-        for name, flags in (("persistent", 0), ("plain", dls.DLS_PLAIN)):
-            dls.dls_count_async(n, flags, spat, sd_pre, len(spre), sd_cnt, d_status, stream)
+        stuned = tuned_launch(n, 0, "order8-diag14")
+        sustained = {"prefixes": len(spre), "leaves": ORDER8_FIXED, "launch": stuned or "library defaults"}
+        for name, flags, settings in (("persistent", 0, stuned), ("plain", dls.DLS_PLAIN, {})):
+            lc = launch_of(dls, settings)
+            dls.dls_count_async_ex(n, flags, spat, sd_pre, len(spre), sd_cnt, d_status, stream, lc)
             torch.cuda.synchronize()
             timer = Timer(torch, stream)
             for _ in range(args.sustained_steps):
                 with timer:
-                    dls.dls_count_async(n, flags, spat, sd_pre, len(spre), sd_cnt, d_status, stream)
+                    dls.dls_count_async_ex(n, flags, spat, sd_pre, len(spre), sd_cnt, d_status, stream, lc)
             s = sd_cnt.sum()
             torch.cuda.synchronize()
             ms = timer.mean_ms()
