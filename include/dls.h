@@ -165,12 +165,18 @@ int dls_count(int n, uint32_t flags, const uint8_t *prefixes, int64_t num,
 /* Launch shape for the *_ex calls; zero fields mean "library default". */
 typedef struct {
     int block;          /* threads per workgroup (64..1024, multiple of 64)   */
-    int blocks_per_cu;  /* persistent kernel: resident workgroups per CU      */
+    int blocks_per_cu;  /* persistent kernel: workgroups per CU in the grid
+                           (0 = 2048 / block).  Workgroups beyond those that
+                           fit at once start when others leave; they still
+                           count in the guided chunk size (remaining tasks /
+                           (2 x waves)), so a larger grid means smaller
+                           chunks.  The expansion default follows it too.  */
     int steal_depth;    /* persistent kernel: give subtrees to idle waves on
                            other CUs only from levels < (levels - steal_depth);
                            0 = library default (on for batches too small to
                            fill the GPU), negative = off                       */
-    int refill_every;   /* persistent kernel: DFS steps between refills       */
+    int refill_every;   /* persistent kernel: DFS steps between refills
+                           (0 = 32; rounded up to an even number)          */
     int order_variant;  /* fill-order variant (see dls_order_variant); 0 =
                            the rule of Sec. 2.3.  Counts never depend on it. */
     int time_kernel;    /* nonzero: record a HIP event pair around the

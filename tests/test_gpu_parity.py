@@ -398,3 +398,49 @@ def test_lds_masks_vs_order10_sample():
     total, cells, pos, opre, ocounts = golden_io.vs10_sample()
     c, st = gpu_counts(dls, 10, dls.DLS_VSYM, opre[:512], launch=LDS_MASKS)
     assert st == 0 and np.array_equal(c, ocounts[:512])
+
+
+# --------------------------------------------------------------------------
+# line masks forced into VGPRs at orders 9 and 10 (two 64-bit words per kind
+# of line); orders >= 9 default to the LDS-mask layout
+# --------------------------------------------------------------------------
+
+VGPR_MASKS = {"lds_masks": -1}
+
+
+@pytest.fixture(scope="module")
+def order9_deep():
+    """256 order-9 prefixes sharing one pattern: the first 28 cells of the
+    fill order assigned (14 at spread positions of the oracle's enumeration,
+    then the first consistent extension), with their oracle counts."""
+    base = oracle.identity_prefix(9)
+    order = oracle.fill_order(9, list(range(9)))
+    total = oracle.count_assignments(9, base, order[:14])
+    p14 = oracle.assignments_at(9, base, order[:14], np.linspace(0, total - 1, 256).astype(np.int64))
+    pattern = np.full(81, 0xFF, dtype=np.uint8)
+    pattern[list(range(9)) + list(order[:28])] = 0
+    pre = []
+    for p in p14:
+        if oracle.count_assignments(9, p, order[14:28]) == 0:
+            continue  # no consistent extension of this one
+        e = oracle.assignments_at(9, p, order[14:28], [0])[0]
+        assert np.array_equal(e == 0xFF, pattern == 0xFF)
+        pre.append(e)
+    pre = np.ascontiguousarray(np.array(pre, dtype=np.uint8))
+    return pre, oracle.count_many(9, pre)
+
+
+@pytest.mark.parametrize("extra", [{}, {"expand_target": -1, "steal_depth": 4, "refill_every": 4},
+                                   {"block": 64, "blocks_per_cu": 1, "refill_every": 2}])
+def test_order9_both_layouts(order9_deep, extra):
+    pre, want = order9_deep
+    assert len(pre) > 200 and want.sum() > 0
+    for layout in (VGPR_MASKS, LDS_MASKS):
+        c, st = gpu_counts(dls, 9, 0, pre, launch={**layout, **extra})
+        assert st == 0 and np.array_equal(c, want), (layout, extra)
+
+
+def test_vgpr_masks_vs_order10_sample():
+    total, cells, pos, opre, ocounts = golden_io.vs10_sample()
+    c, st = gpu_counts(dls, 10, dls.DLS_VSYM, opre[:512], launch=VGPR_MASKS)
+    assert st == 0 and np.array_equal(c, ocounts[:512])
