@@ -196,12 +196,12 @@ def main(argv=None):
                  space={"order_variant": VARIANTS, "block": BLOCKS, "refill_every": REFILLS, "lds_masks": (-1, 1)},
                  default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1}, save=False)
         first = {k: v for k, v in r["best"].items() if k != "ms"}
-        # stage 2: grid size (1x, 1.5x, 2x the resident default; waves beyond
+        # stage 2: grid size (1x to 4x the resident default; waves beyond
         # the resident ones only shrink the guided chunks) and smallest chunk
         d = 2048 // first["block"]
         r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
-                 space={**{k: (v,) for k, v in first.items()}, "blocks_per_cu": (0, d * 3 // 2, d * 2),
-                        "chunk_min": (0, 2, 4, 16)},
+                 space={**{k: (v,) for k, v in first.items()}, "blocks_per_cu": (0, d * 2, d * 3, d * 4),
+                        "chunk_min": (0, 4, 16, 64)},
                  default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1})
         print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
                           "plain_ms": r["plain_ms"]}), flush=True)
