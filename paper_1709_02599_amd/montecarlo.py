@@ -104,20 +104,34 @@ def completions(n: int, squares: np.ndarray, launch=None) -> np.ndarray:
     return d_cnt.cpu().numpy().view(np.uint64).copy()
 
 
-def estimate(n: int, k: int, samples: int, rng, launch=None) -> dict:
+def estimate(n: int, k: int, samples: int, rng, launch=None, batch: Optional[int] = None, log=None) -> dict:
+    """Draw `samples` squares and count their completions, `batch` at a time
+    (all at once by default); `log` receives a progress line per batch.  The
+    draws depend only on the generator, not on the batching."""
     t0 = time.perf_counter()
     s = Sampler(n, k)
     t1 = time.perf_counter()
-    drawn = np.stack([s.draw(rng) for _ in range(samples)])
-    t2 = time.perf_counter()
-    c = completions(n, drawn, launch)
-    t3 = time.perf_counter()
+    batch = batch or samples
+    parts, draw_s, count_s = [], 0.0, 0.0
+    for b0 in range(0, samples, batch):
+        ta = time.perf_counter()
+        drawn = np.stack([s.draw(rng) for _ in range(min(batch, samples - b0))])
+        tb = time.perf_counter()
+        parts.append(completions(n, drawn, launch))
+        tc = time.perf_counter()
+        draw_s += tb - ta
+        count_s += tc - tb
+        if log:
+            done = np.concatenate(parts).astype(np.float64)
+            log(f"{len(done)}/{samples} samples: mean completions {done.mean():.4e}, "
+                f"estimate {s.total * done.mean():.4e}, batch {tc - ta:.1f} s")
+    c = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint64)
     x = c.astype(np.float64)
     mean = float(x.mean())
     se = float(x.std(ddof=1) / math.sqrt(len(x))) if len(x) > 1 else float("nan")
     return {"n": n, "k": k, "N_k": s.total, "samples": samples, "mean_completions": mean,
             "estimate": s.total * mean, "std_error": s.total * se, "squares_counted": int(c.sum()),
-            "seconds": {"count_N_k": t1 - t0, "draw": t2 - t1, "complete": t3 - t2},
+            "seconds": {"count_N_k": t1 - t0, "draw": draw_s, "complete": count_s},
             "completions": [int(v) for v in c]}
 
 
@@ -134,8 +148,10 @@ def main(argv=None):
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--samples", type=int, default=64)
     ap.add_argument("--seed", type=int, default=dls_workloads.DEFAULT_SEED)
+    ap.add_argument("--batch", type=int, default=16, help="samples counted per GPU batch")
     args = ap.parse_args(argv)
-    r = estimate(args.n, args.k, args.samples, dls_workloads.SplitMix64(args.seed))
+    r = estimate(args.n, args.k, args.samples, dls_workloads.SplitMix64(args.seed), batch=args.batch,
+                 log=lambda line: print(line, flush=True))
     r.pop("completions")
     print(json.dumps(r), flush=True)
 

@@ -48,3 +48,13 @@ def test_estimate_of_order7_is_unbiased():
     assert abs(r["estimate"] - exact) < 4 * r["std_error"], r
     # the per-sample completion counts are exact counts of the drawn squares
     assert r["squares_counted"] == sum(r["completions"])
+
+
+def test_batched_estimate_draws_the_same_samples():
+    from paper_1709_02599_amd.montecarlo import estimate
+    n, k = 7, 14
+    whole = estimate(n, k, 40, workloads.SplitMix64(5))
+    lines = []
+    parts = estimate(n, k, 40, workloads.SplitMix64(5), batch=7, log=lines.append)
+    assert parts["completions"] == whole["completions"]
+    assert parts["estimate"] == whole["estimate"] and len(lines) == 6
