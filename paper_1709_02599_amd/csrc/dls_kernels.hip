@@ -510,7 +510,11 @@ struct VLane {
     }
 
     // One DFS step, taken by every lane of the wave (see LdsLane::step for
-    // the parked lanes).  nsa = nda * kst + sc0 (kst = stride / 8).
+    // the parked lanes).  nsa = nda * kst + sc0 (kst = stride / 8).  Up to
+    // N = 8 bits 8-15 of y hold a keep mask: AllN, and 0 at the last level,
+    // whose candidates are counted instead of entered; no lane is ever
+    // parked at the last level (see from_rec), so an up step never lands on
+    // it and needs no guard.
     template <class S>
     __device__ __forceinline__ void step(uint32_t kst, uint32_t sc0, uint32_t da_last) {
         const bool up = (cand == 0u);
@@ -523,9 +527,15 @@ struct VLane {
         const uint32_t b = stored & (0u - stored);
         toggle(up ? nd : cur, b);
         const uint32_t nc = cands(nd);
-        const bool leaf = (nda == da_last) && !up;
-        c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
-        cand = up ? (stored ^ b) : (leaf ? 0u : nc);
+        if constexpr (N <= 8) {
+            const uint32_t keep = (nd.y >> 8) & 0xFFu;
+            c32 += (uint32_t)__builtin_popcount(nc & ~keep);
+            cand = up ? (stored ^ b) : (nc & keep);
+        } else {
+            const bool leaf = (nda == da_last) && !up;
+            c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
+            cand = up ? (stored ^ b) : (leaf ? 0u : nc);
+        }
         cur = nd;
         da = nda;
         sa = nsa;
@@ -553,13 +563,15 @@ struct VLane {
             return;
         }
         cand = r.cl & 0xFFFFu;
-        da = da0 = dbase + 8u * lvl;
-        sa = lane_off + lvl * stride;
-        cur = lds_ld2(da);
+        uint32_t at = lvl;
         if ((int)lvl == last) {
             c32 = (uint32_t)__builtin_popcount(cand);
             cand = 0u;
+            at = lvl - 1u;  // parked one level up (the plan has at least two levels)
         }
+        da = da0 = dbase + 8u * at;
+        sa = lane_off + at * stride;
+        cur = lds_ld2(da);
     }
 
     // Give away the untried siblings at level lvl: the record holds the
@@ -596,7 +608,10 @@ __device__ __forceinline__ void vl_build_desc(const Plan &plan, unsigned char *s
     uint2 *t = reinterpret_cast<uint2 *>(smem);
     for (int k = threadIdx.x; k < plan.nlev; k += blockDim.x) {
         const uint32_t d = plan.desc[k];
-        t[k] = make_uint2((d & 0xFFu) | ((d_md(d) & G::ALL) << 16), ((d >> 8) & 0xFFu) | ((d_ad(d) & G::ALL) << 16));
+        // keep mask (N <= 8): AllN except at the last level
+        const uint32_t keep = (N <= 8 && k != plan.nlev - 1) ? (G::ALL << 8) : 0u;
+        t[k] = make_uint2((d & 0xFFu) | ((d_md(d) & G::ALL) << 16),
+                          ((d >> 8) & 0xFFu) | keep | ((d_ad(d) & G::ALL) << 16));
     }
 }
 
