@@ -225,18 +225,12 @@ struct Lane {
 template <int N>
 using StackT = typename std::conditional<(N <= 8), uint8_t, uint16_t>::type;
 
-// LDS layout of the search kernels: level descriptors, then the stacks, then
-// (persistent kernel, line masks in VGPRs) one mailbox of 64 task records per
-// wave for sharing work in the tail
+// LDS layout of the plain kernel: 4-byte level descriptors, then the stacks
+// (the persistent kernel's layouts follow LdsLane and VLane below)
 constexpr uint32_t kStackBase = sizeof(uint32_t) * kMaxLevels;
-#ifndef DLS_LM_PACK_MIN_N
-#define DLS_LM_PACK_MIN_N 9
-#endif
-
-__host__ __device__ inline uint32_t stacks_end(int nlev, int block, int elem) {
-    const uint32_t end = kStackBase + (uint32_t)elem * (uint32_t)(nlev > 1 ? nlev : 1) * (uint32_t)block;
-    return (end + 15u) & ~15u;
-}
+// from this order on, the LDS-mask layout packs a row and a column mask into
+// one word (see LdsLane)
+constexpr int kLmPackMinN = 9;
 
 // LDS layout with the line masks in LDS (LdsLane): a table of 16-byte level
 // descriptors (8 bytes, one per level of the plan), then the row and column masks (one
@@ -269,7 +263,7 @@ struct LdsLane {
     // PACK: LDS word k of a lane holds row k's mask in bits 0-15 and column
     // k's mask in bits 16-31 (half the LDS, one shift more per toggle and
     // read); otherwise one word per row, then one per column
-    static constexpr bool PACK = N >= DLS_LM_PACK_MIN_N;
+    static constexpr bool PACK = N >= kLmPackMinN;
     static constexpr int LINES = PACK ? N : N + G::NCOL;
     static constexpr uint32_t CSH = PACK ? 16u : 0u;  // column mask position in its word
     // Level descriptors: 8 bytes {row word offset | column word offset << 16,
@@ -943,10 +937,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             // store is the final one) instead of adding atomically.  Tasks come
             // from a wave-private range refilled with a guided chunk
             // (remaining / (2 * waves), at least chunk_min) by one atomic on
-            // ctrl->head.  Every
-            // lane issues the same memory operations (one record load, then
-            // one count store), so the wait below covers the loads only.
-            if (want && (__popcll(want) >= tune.refill_min || want == ~0ull)) {
+            // ctrl->head.  Every lane issues the same memory operations (one
+            // record load, then one count store), so the wait below covers
+            // the loads only.
+            if (want && ((int)__popcll(want) >= tune.refill_min || want == ~0ull)) {
                 const bool idle = !has || fin;
                 const uint64_t k = (uint64_t)__popcll(want);
                 const uint64_t rank = (uint64_t)__popcll(want & below);
@@ -1773,7 +1767,7 @@ size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent, bool lds_
     const int elem = n <= 8 ? 1 : 2;
     if (!persistent) return kStackBase + (size_t)elem * (size_t)(nlev > 1 ? nlev : 1) * block;
     if (lds_masks) {
-        const int lines = n >= DLS_LM_PACK_MIN_N ? n : n + (vs ? (n + 1) / 2 : n);  // LdsLane<n, vs>::LINES
+        const int lines = n >= kLmPackMinN ? n : n + (vs ? (n + 1) / 2 : n);  // LdsLane<n, vs>::LINES
         return lm_stacks_end(lines, nlev, block, elem, vs);
     }
     return vl_stacks_end(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
