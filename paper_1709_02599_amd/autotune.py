@@ -97,9 +97,11 @@ def time_launch(n: int, flags: int, pattern, d_pre, num: int, d_cnt, d_st, strea
 
 
 def tune(n: int, flags: int, prefixes: np.ndarray, workload: str, space: Optional[Dict[str, Iterable]] = None,
-         default: Optional[dict] = None, reps: int = 3, save: bool = True, verbose: bool = True) -> dict:
+         default: Optional[dict] = None, reps: int = 3, save: bool = True, verbose: bool = True,
+         plain: bool = True) -> dict:
     """Time every combination of the launch settings in `space` (field ->
-    candidate values); all must give identical counts.  Keeps the fastest."""
+    candidate values); all must give identical counts.  Keeps the fastest.
+    plain: also time the plain kernel for reference (slow on big subtrees)."""
     import torch
     space = space or {"order_variant": VARIANTS, "block": BLOCKS, "refill_every": REFILLS}
     default = default or {"order_variant": 0, "block": 256, "refill_every": 32}
@@ -127,10 +129,12 @@ def tune(n: int, flags: int, prefixes: np.ndarray, workload: str, space: Optiona
         if verbose:
             print(f"  {settings}: {ms:.3f} ms", flush=True)
     # the plain kernel under the paper's order, for reference
-    plain_ms, digest, _ = time_launch(n, flags | DLS_PLAIN, pattern, d_pre, num, d_cnt, d_st, stream,
-                                      {"block": 256}, reps)
-    if digest != ref:
-        raise RuntimeError("plain kernel counts differ")
+    plain_ms = None
+    if plain:
+        plain_ms, digest, _ = time_launch(n, flags | DLS_PLAIN, pattern, d_pre, num, d_cnt, d_st, stream,
+                                          {"block": 256}, reps)
+        if digest != ref:
+            raise RuntimeError("plain kernel counts differ")
     table.sort(key=lambda r: r["ms"])
     dflt = [r for r in table if all(r.get(k) == v for k, v in default.items())]
     result = {"best": table[0], "default": dflt[0] if dflt else None, "plain_ms": plain_ms,
@@ -223,6 +227,19 @@ def main(argv=None):
         s = tune(8, 0, spre, "order8-diag14", space={"order_variant": (0, 1, 2, 3, 5, 6)},
                  default={"order_variant": 0}, reps=1)
         print(json.dumps({"workload": "order8-diag14", "best": s["best"], "default": s["default"]}), flush=True)
+
+    if want("order9-sample"):
+        # 1 500 seeded workunits of the order-9 hourglass split (the full
+        # count's workload); fullcount.py takes its launch from this entry
+        import sys
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import dls_workloads
+        p9, _ = dls_split(9, DLS_SYMBREAK, 22)
+        pos = np.array(dls_workloads.sample_positions(len(p9), 1500, seed=7), dtype=np.int64)
+        s = tune(9, 0, np.ascontiguousarray(p9[pos]), "order9-sample",
+                 space={"order_variant": (0, 2, 5), "refill_every": (32, 64, 128)},
+                 default={"order_variant": 0, "refill_every": 32}, reps=1, plain=False)
+        print(json.dumps({"workload": "order9-sample", "best": s["best"], "default": s["default"]}), flush=True)
 
 
 if __name__ == "__main__":

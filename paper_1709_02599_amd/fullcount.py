@@ -136,7 +136,8 @@ def main(argv=None):
     ap.add_argument("--chunks", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--batches", type=int, default=10)
-    ap.add_argument("--launch", default="{}", help="launch settings as JSON, e.g. '{\"order_variant\": 2}'")
+    ap.add_argument("--launch", default="{}", help="launch settings as JSON, e.g. '{\"order_variant\": 2}'; "
+                    "empty: the autotuner's order9-sample entry for order 9 with --symbreak")
     ap.add_argument("--out", default="fullcount_out")
     ap.add_argument("--merge", default=None, help="sum the chunk files of this directory")
     args = ap.parse_args(argv)
@@ -144,8 +145,15 @@ def main(argv=None):
         print(json.dumps(merge(args.merge)), flush=True)
         return
     flags = (DLS_SYMBREAK if args.symbreak else 0) | (DLS_VSYM if args.vsym else 0)
+    launch = json.loads(args.launch)
+    if not launch and args.n == 9 and flags == DLS_SYMBREAK:
+        # the autotuner's launch for a sample of this workload, if tuned here
+        from . import autotune
+        tuned = autotune.best(9, 0, "order9-sample")
+        launch = {k: v for k, v in (tuned or {}).items() if k != "ms"}
+    print(f"launch: {launch or 'library defaults'}", flush=True)
     st = run_chunk(args.n, flags, args.depth, args.chunk, args.chunks, args.out, args.batches,
-                   json.loads(args.launch), log=lambda s: print(s, flush=True))
+                   launch, log=lambda s: print(s, flush=True))
     print(json.dumps(st), flush=True)
 
 
