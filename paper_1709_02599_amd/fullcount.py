@@ -37,20 +37,39 @@ def split_digest(pre: np.ndarray, mult: np.ndarray) -> str:
     return h.hexdigest()
 
 
+def load_split(n: int, flags: int, depth: int, cache: str | None = None):
+    """dls_split(n, flags, depth), optionally through a cache file (plain
+    .npz, no pickled objects) so that the chunks of one count split once.
+    A cache whose recorded parameters or digest do not match is rebuilt."""
+    if cache and os.path.exists(cache):
+        with np.load(cache, allow_pickle=False) as z:
+            if (int(z["n"]), int(z["flags"]), int(z["depth"])) == (n, flags, depth):
+                pre, mult = z["pre"], z["mult"]
+                if split_digest(pre, mult) == str(z["digest"]):
+                    return pre, mult
+    pre, mult = dls_split(n, flags, depth)
+    if cache:
+        tmp = cache + ".tmp.npz"
+        np.savez(tmp, n=n, flags=flags, depth=depth, pre=pre, mult=mult, digest=split_digest(pre, mult))
+        os.replace(tmp, cache)
+    return pre, mult
+
+
 def _path(out: str, chunk: int, chunks: int) -> str:
     return os.path.join(out, f"chunk_{chunk:04d}_of_{chunks:04d}.json")
 
 
 def run_chunk(n: int, flags: int, depth: int, chunk: int, chunks: int, out: str, batches: int = 10,
-              launch: dict | None = None, log=print, stop_after: int | None = None) -> dict:
+              launch: dict | None = None, log=print, stop_after: int | None = None,
+              split_cache: str | None = None) -> dict:
     """Count chunk `chunk` of `chunks`; resumes from the chunk file in `out`
     if one exists.  stop_after: return after that many batches of this call
-    (the file records the progress)."""
+    (the file records the progress).  split_cache: see load_split."""
     import torch
     os.makedirs(out, exist_ok=True)
     path = _path(out, chunk, chunks)
     t0 = time.perf_counter()
-    pre, mult = dls_split(n, flags, depth)
+    pre, mult = load_split(n, flags, depth, split_cache)
     digest = split_digest(pre, mult)
     log(f"split: {len(pre)} workunits in {time.perf_counter() - t0:.1f} s, digest {digest[:16]}")
     state = {"n": n, "flags": flags, "depth": depth, "chunk": chunk, "chunks": chunks,
@@ -139,6 +158,7 @@ def main(argv=None):
     ap.add_argument("--launch", default="{}", help="launch settings as JSON, e.g. '{\"order_variant\": 2}'; "
                     "empty: the autotuner's order9-sample entry for order 9 with --symbreak")
     ap.add_argument("--out", default="fullcount_out")
+    ap.add_argument("--split-cache", default=None, help="file holding the split, shared by the chunks")
     ap.add_argument("--merge", default=None, help="sum the chunk files of this directory")
     args = ap.parse_args(argv)
     if args.merge:
@@ -153,7 +173,7 @@ def main(argv=None):
         launch = {k: v for k, v in (tuned or {}).items() if k != "ms"}
     print(f"launch: {launch or 'library defaults'}", flush=True)
     st = run_chunk(args.n, flags, args.depth, args.chunk, args.chunks, args.out, args.batches,
-                   launch, log=lambda s: print(s, flush=True))
+                   launch, log=lambda s: print(s, flush=True), split_cache=args.split_cache)
     print(json.dumps(st), flush=True)
 
 

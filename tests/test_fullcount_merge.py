@@ -47,3 +47,29 @@ def test_merge_rejects_mixed_splits(tmp_path):
 def test_merge_needs_files(tmp_path):
     with pytest.raises(RuntimeError):
         fullcount.merge(os.path.join(str(tmp_path), "none"))
+
+
+def test_split_cache_round_trip_and_rebuild(tmp_path, monkeypatch):
+    import numpy as np
+    from paper_1709_02599_amd import DLS_SYMBREAK, dls_split
+    cache = str(tmp_path / "split7.npz")
+    pre0, mult0 = dls_split(7, DLS_SYMBREAK, 16)
+    pre1, mult1 = fullcount.load_split(7, DLS_SYMBREAK, 16, cache)      # computes, writes
+    assert os.path.exists(cache)
+    def no_split(*args):
+        raise AssertionError("split recomputed although cached")
+    with monkeypatch.context() as m:
+        m.setattr(fullcount, "dls_split", no_split)
+        pre2, mult2 = fullcount.load_split(7, DLS_SYMBREAK, 16, cache)  # reads
+    for a, b in ((pre0, pre1), (pre0, pre2), (mult0, mult1), (mult0, mult2)):
+        assert np.array_equal(a, b)
+    # another split's parameters: rebuilt, not reused
+    pre3, _ = fullcount.load_split(7, DLS_SYMBREAK, 17, cache)
+    assert np.array_equal(pre3, dls_split(7, DLS_SYMBREAK, 17)[0])
+    # a tampered cache fails its digest and is rebuilt
+    with np.load(cache) as z:
+        d = {k: z[k] for k in z.files}
+    d["mult"] = d["mult"] + 1
+    np.savez(cache, **d)
+    pre4, mult4 = fullcount.load_split(7, DLS_SYMBREAK, 17, cache)
+    assert np.array_equal(mult4, dls_split(7, DLS_SYMBREAK, 17)[1])
