@@ -232,11 +232,11 @@ constexpr uint32_t kStackBase = sizeof(uint32_t) * kMaxLevels;
 // one word (see LdsLane)
 constexpr int kLmPackMinN = 9;
 
-// LDS layout with the line masks in LDS (LdsLane): a table of 16-byte level
-// descriptors (8 bytes, one per level of the plan), then the row and column masks (one
-// 32-bit word per line and lane, lines apart by `lstride` = 4 * block bytes,
-// lanes side by side), then the stacks.  LDS per lane
-// sets the occupancy of this layout, so nothing is sized for the maximum.
+// LDS layout with the line masks in LDS (LdsLane): a table of level
+// descriptors (8 bytes each, 16 with VS; one per level of the plan), then the
+// row and column masks (one 32-bit word per line and lane, lines apart by
+// `lstride` = 4 * block bytes, lanes side by side), then the stacks.  LDS per
+// lane sets the occupancy of this layout, so nothing is sized for the maximum.
 __host__ __device__ inline uint32_t lm_desc_bytes(int nlev, bool vs) {
     return ((vs ? 16u : 8u) * (uint32_t)(nlev > 1 ? nlev : 1) + 15u) & ~15u;
 }
@@ -254,9 +254,9 @@ __host__ __device__ inline uint32_t lm_stacks_end(int lines, int nlev, int block
 // Lane state with the row and column masks in LDS instead of VGPRs.  A value
 // is marked or cleared with one LDS xor per line (ds_xor_b32), so the packed
 // 64-bit words and their word selection disappear from the search loop;
-// only the diagonal masks stay in registers.  The level descriptor is 16
-// bytes: LDS offsets of the cell's row and column mask words and the
-// diagonal selectors as all-ones / zero masks.
+// only the diagonal masks stay in registers.  A level descriptor holds the
+// LDS offsets of the cell's row and column mask words and the diagonal
+// selectors as all-ones / zero masks (layouts below).
 template <int N, bool VS>
 struct LdsLane {
     using G = Geo<N, VS>;
