@@ -302,3 +302,141 @@ def test_count_assignments_brute_force_rows():
     two = sum(1 for p in perms for q in perms if ok([r0, p, q]))
     assert oracle.count_assignments(n, base, list(range(n, 2 * n))) == one
     assert oracle.count_assignments(n, base, list(range(n, 3 * n))) == two
+
+
+# --------------------------------------------------------------------------
+# positional selection of workunits (Sec. 5.3 random sampling of a split)
+# --------------------------------------------------------------------------
+
+def _set_based_list(n, base, cells):
+    """Every consistent assignment of `cells` on top of `base`, listed in
+    depth-first order with values increasing, built from Python sets (no
+    oracle code): the order in which the workunits of Sec. 5.2 are listed."""
+    sq = {(c // n, c % n): int(v) for c, v in enumerate(base) if v != E}
+    out = []
+
+    def clash(i, j, v):
+        for (a, b), w in sq.items():
+            if w == v and (a == i or b == j or (i == j and a == b)
+                           or (i + j == n - 1 and a + b == n - 1)):
+                return True
+        return False
+
+    def rec(k):
+        if k == len(cells):
+            sqr = np.full(n * n, E, dtype=np.uint8)
+            for (a, b), w in sq.items():
+                sqr[a * n + b] = w
+            out.append(sqr)
+            return
+        i, j = divmod(cells[k], n)
+        for v in range(n):
+            if not clash(i, j, v):
+                sq[(i, j)] = v
+                rec(k + 1)
+                del sq[(i, j)]
+    rec(0)
+    return np.array(out, dtype=np.uint8).reshape(-1, n * n)
+
+
+@pytest.mark.parametrize("n,k", [(5, 6), (6, 7), (7, 6)])
+def test_assignments_at_matches_set_based_list(n, k):
+    base = oracle.identity_prefix(n)
+    cells = oracle.fill_order(n)[:k]
+    ref = _set_based_list(n, base, cells)
+    total = len(ref)
+    assert total > 2
+    rng = np.random.default_rng(17 + n)
+    pos = np.unique(np.concatenate([[0, total - 1], rng.integers(0, total, size=min(40, total))]))
+    got = oracle.assignments_at(n, base, cells, pos)
+    assert np.array_equal(got, ref[pos])
+    # the whole list, and the list the full enumeration gives
+    assert np.array_equal(oracle.assignments_at(n, base, cells, np.arange(total)), ref)
+    assert np.array_equal(oracle.assignments(n, base, cells), ref)
+
+
+@pytest.mark.parametrize("n,k,vs", [(5, 6, False), (6, 6, False), (7, 5, False), (6, 4, True), (8, 5, True)])
+def test_assignments_at_matches_full_enumeration(n, k, vs):
+    base = oracle.identity_prefix(n)
+    cells = oracle.fill_order(n, vs=vs)[:k]
+    full = oracle.assignments(n, base, cells, vs=vs)
+    total = len(full)
+    assert total > 2
+    # first, last, and a spread of positions in between
+    pos = np.unique(np.linspace(0, total - 1, min(total, 25)).astype(np.int64))
+    assert np.array_equal(oracle.assignments_at(n, base, cells, pos, vs=vs), full[pos])
+    assert np.array_equal(oracle.assignments_at(n, base, cells, [total - 1], vs=vs), full[-1:])
+    assert np.array_equal(oracle.assignments_at(n, base, cells, [0], vs=vs), full[:1])
+
+
+def test_assignments_at_rejects_unordered_positions():
+    n = 5
+    with pytest.raises(ValueError):
+        oracle.assignments_at(n, oracle.identity_prefix(n), oracle.fill_order(n)[:3], [3, 1])
+
+
+# --------------------------------------------------------------------------
+# normalisation of vertically symmetric counts
+# --------------------------------------------------------------------------
+
+def test_vs_unnormalised_order6():
+    # brute force over whole VS rows, no first-row normalisation, against
+    # fixed-first-row count x 2^(N/2) (N/2)!; at N = 6 the alternatives
+    # 2^(N-1) and N!/3 give other totals, so the formula itself is pinned
+    n = 6
+    fixed = oracle.count(n, oracle.identity_prefix(n), vs=True)
+    brute = oracle.brute_force_count(n, normalized=False, vs=True)
+    assert brute == oracle.total_from_fixed(n, fixed, vs=True) == 3072
+    assert brute != fixed * 2 ** (n - 1) and brute != fixed * math.factorial(n) // 3
+
+
+def test_vs_first_rows_are_equally_frequent():
+    # the relabellings that commute with v -> N-1-v act transitively on the
+    # VS first rows, so every VS first row has the same number of completions
+    import itertools
+    n = 6
+    base = oracle.count(n, oracle.identity_prefix(n), vs=True)
+    rows = [p for p in itertools.permutations(range(n))
+            if all(p[j] + p[n - 1 - j] == n - 1 for j in range(n))]
+    assert len(rows) == 2 ** (n // 2) * math.factorial(n // 2)
+    for r in rows[::7]:
+        pre = np.full(n * n, E, dtype=np.uint8)
+        pre[:n] = r
+        assert oracle.count(n, pre, vs=True) == base
+
+
+# --------------------------------------------------------------------------
+# fill-order readings that no printed value fixes (VS, hourglass first)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [6, 8, 10])
+def test_vs_fill_order_covers_left_half_once(n):
+    order = oracle.fill_order(n, vs=True)
+    left = [i * n + j for i in range(1, n) for j in range(n) if 2 * j < n]
+    assert sorted(order) == left
+
+
+@pytest.mark.parametrize("n,vs", [(7, False), (8, False), (8, True)])
+def test_hourglass_first_fill_order(n, vs):
+    hc = set(oracle.hourglass_cells(n))
+    order = oracle.fill_order(n, vs=vs, first=hc)
+    inside = [c for c in order if c in hc or (vs and (c // n) * n + n - 1 - c % n in hc)]
+    k = len(inside)
+    assert order[:k] == inside
+    # the rest is the unconstrained rule applied after the hourglass cells
+    rest = oracle.fill_order(n, list(range(n)) + [c for c in range(n * n) if c in hc or
+                                                    (vs and (c // n) * n + n - 1 - c % n in hc)], vs=vs)
+    assert order[k:] == rest
+
+
+@pytest.mark.parametrize("n,vs,k", [(7, False, 9), (8, True, 8)])
+def test_split_set_independent_of_order(n, vs, k):
+    # the workunits on a set of cells do not depend on the order in which
+    # those cells are listed (only their listing order does)
+    base = oracle.identity_prefix(n)
+    cells = oracle.fill_order(n, vs=vs)[:k]
+    a = oracle.assignments(n, base, cells, vs=vs)
+    b = oracle.assignments(n, base, cells[::-1], vs=vs)
+    sa = sorted(map(bytes, a))
+    assert sa == sorted(map(bytes, b))
+    assert int(oracle.count_many(n, a, vs=vs).sum()) == oracle.count(n, base, vs=vs)
