@@ -7,6 +7,9 @@ apart from either.
 * ``SplitMix64`` -- the counter-based generator of Steele, Lea and Flood
   (2014): state += 0x9E3779B97F4A7C15, then two xor-shift-multiply rounds.
 * ``sample_positions`` -- k distinct positions in [0, P), uniform, sorted.
+* ``random_permutations`` -- uniform permutations (Fisher-Yates), e.g. the
+  order in which a search tries values when it builds a complete square;
+  ``blank_cells`` -- a square with uniformly drawn cells emptied.
 * ``random_job`` -- a serving request: order N, flags, and a prefix made of the
   identity first row plus k random cells, each a random empty cell given a
   random value that repeats no value already in its row, column or diagonal
@@ -47,6 +50,32 @@ class SplitMix64:
 
     def uniform(self) -> float:
         return (self.next() >> 11) * (1.0 / (1 << 53))
+
+
+def random_permutations(n: int, count: int, rng: SplitMix64) -> np.ndarray:
+    """count uniform random permutations of 0..n-1 ([count, n] uint8,
+    Fisher-Yates)."""
+    out = np.zeros((count, n), dtype=np.uint8)
+    for r in range(count):
+        p = list(range(n))
+        for t in range(n - 1, 0, -1):
+            u = rng.below(t + 1)
+            p[t], p[u] = p[u], p[t]
+        out[r] = p
+    return out
+
+
+def blank_cells(n: int, square: np.ndarray, k: int, vs: bool, rng: SplitMix64) -> np.ndarray:
+    """A copy of `square` with k uniformly drawn cells emptied (for vs, k
+    left-half cells together with their mirrors)."""
+    sq = np.array(square, dtype=np.uint8).reshape(n * n).copy()
+    cand = [c for c in range(n * n) if not vs or 2 * (c % n) < n - 1]
+    for pos in sample_positions(len(cand), min(k, len(cand)), seed=rng.next()):
+        c = cand[int(pos)]
+        sq[c] = EMPTY
+        if vs:
+            sq[(c // n) * n + n - 1 - c % n] = EMPTY
+    return sq
 
 
 def sample_positions(total: int, k: int, seed: int = DEFAULT_SEED) -> np.ndarray:

@@ -152,15 +152,55 @@ int64_t dls_group_order(int n);
 int dls_canon(int n, const uint8_t *h, uint32_t *mult_out);
 
 /*
- * Exact counts on the GPU, host buffers, blocking.  prefixes: [num][n*n];
- * counts_out: [num] uint64, counts_out[k] = number of DLS (VS-DLS with
- * DLS_VSYM) agreeing with prefixes[k].  Prefixes may differ in which cells
- * are assigned; they are grouped by pattern internally.  DLS_PLAIN selects
- * the plain kernel.  With DLS_VSYM and odd n > 1 every count is 0 and nothing
- * is launched.
+ * Exact counts on the GPU, host buffers, blocking.  The count of a prefix is
+ * the number of squares that satisfy the definition of Sec. 1 (every row,
+ * column, the main diagonal and the main antidiagonal a permutation of
+ * 0..n-1; with DLS_VSYM also a[i][j] + a[i][n-1-j] = n-1) and agree with the
+ * prefix on its assigned cells: the answer to one workunit of Sec. 5.2, whose
+ * sum over a split is the count of the parent.
+ * prefixes: [num][n*n] uint8 (DLS_EMPTY = unassigned); counts_out: [num]
+ * uint64, counts_out[k] = the count of prefixes[k].  Prefixes may differ in
+ * which cells are assigned; they are grouped by pattern internally (with
+ * DLS_VSYM each prefix is first completed by mirror pairs; an inconsistent
+ * pair counts 0).  DLS_PLAIN selects the plain kernel.  With DLS_VSYM and
+ * odd n > 1 every count is 0 and nothing is launched.  Errors: DLS_EINVAL
+ * (bad n, flags, cell value, NULL buffer with num > 0), DLS_ENOMEM,
+ * DLS_EDEVICE (HIP error, or a kernel reported lost work).
  */
 int dls_count(int n, uint32_t flags, const uint8_t *prefixes, int64_t num,
               uint64_t *counts_out);
+
+/*
+ * The same counts (Sec. 1 definition, one integer per Sec. 5.2 workunit) on
+ * device buffers, asynchronous on `stream` (a hipStream_t; NULL = the null
+ * stream).  d_prefixes: device [num][n*n] uint8; d_counts: device [num]
+ * uint64, overwritten once the stream reaches the work.  Both stay the
+ * caller's; the library keeps no pointer to them after the work completes.
+ * One fill order serves the batch, so every prefix must assign the same cells
+ * as prefix 0 (with DLS_VSYM each assigned cell's mirror assigned too).  The
+ * call reads that pattern from d_prefixes[0] with an n*n-byte device-to-host
+ * copy on `stream` (which waits for the work already queued there), then
+ * enqueues the count and returns.  A prefix that assigns other cells counts
+ * 0 and sets bit 0 of the stream's status word; a task lost to an expired
+ * bounded wait sets bit 1 (its count is then short), an expansion overflow
+ * bit 2: read the word with dls_stream_status after the work.  Under HIP
+ * graph capture this call returns DLS_ECAPTURE (the pattern copy cannot be
+ * captured): use dls_count_async_ex with an explicit pattern.  Other errors
+ * as dls_count, returned before anything is enqueued.
+ */
+int dls_count_async(int n, uint32_t flags, const uint8_t *d_prefixes, int64_t num,
+                    uint64_t *d_counts, void *stream);
+
+/*
+ * Status word of the counting calls made on `stream` without a d_status
+ * buffer (dls_count_async, and the *_ex forms given d_status = NULL): waits
+ * for the stream, writes the OR of the bits those calls set since the last
+ * read to *status_out (0 = every count is exact) and clears it.  Bit 0
+ * (value 1): a prefix did not match the pattern (counted 0); bit 1 (2): a
+ * bounded wait expired (a count is short); bit 2 (4): an expansion buffer
+ * overflowed.  DLS_ECAPTURE under capture.
+ */
+int dls_stream_status(void *stream, uint32_t *status_out);
 
 /* Launch shape for the *_ex calls; zero fields mean "library default". */
 typedef struct {
@@ -244,19 +284,15 @@ int dls_hourglass_classes_async(int n, const uint8_t *d_designs, int64_t num, ui
 int dls_kernel_time_ms(void *stream, float *ms_out, int64_t *launches_out);
 
 /*
- * Exact counts on the GPU, device buffers, asynchronous on `stream`
- * (a hipStream_t; NULL = default stream).  All prefixes must assign exactly
- * the cells marked in `pattern` (host array of n*n bytes, nonzero = assigned;
- * NULL = "row 0 only"), so that one fill order serves the whole batch.
- * d_prefixes: device [num][n*n] uint8; d_counts: device [num] uint64,
- * overwritten.  d_status: optional device uint32, OR-ed with 1 if a prefix
- * does not match the pattern (its count is then 0) and with 2 if the
- * persistent kernel's bounded waits expired; may be NULL.
+ * dls_count_async with the batch's pattern and a status buffer given by the
+ * caller, and an optional launch shape (NULL = library defaults); nothing is
+ * copied back, so these forms can be captured in a HIP graph once the
+ * stream's scratch has been sized by an uncaptured call.  pattern: host array
+ * of n*n bytes, nonzero = assigned in every prefix (NULL = "row 0 only").
+ * d_status: device uint32, OR-ed with the bits listed at dls_stream_status;
+ * NULL = the stream's own status word (read with dls_stream_status).
  * Returns after enqueueing (host-side argument errors are returned at once).
  */
-int dls_count_async(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes,
-                    int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream);
-
 int dls_count_async_ex(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes,
                        int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream,
                        const dls_launch *launch);

@@ -73,6 +73,8 @@ def _load():
     lib.oracle_assignments_at.argtypes = [ctypes.c_int, ctypes.c_int, u8p,
                                           ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, u8p]
+    lib.oracle_first.restype = ctypes.c_int
+    lib.oracle_first.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p, ctypes.c_int64, u8p]
     lib.oracle_hourglass_group.restype = ctypes.c_int
     lib.oracle_hourglass_group.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int8),
                                            ctypes.POINTER(ctypes.c_int8), ctypes.c_int]
@@ -133,6 +135,24 @@ def count_many(n: int, prefixes: np.ndarray, vs: bool = False,
     if r != 0:
         raise ValueError("invalid oracle input")
     return out
+
+
+def first_completion(n: int, cells, value_order=None, vs: bool = False,
+                     node_limit: int = 10_000_000) -> Optional[np.ndarray]:
+    """One square agreeing with ``cells`` (the same search as ``count``,
+    stopped at the first square), or None if there is none.  ``value_order``
+    [n*n, n]: per cell, the order in which values are tried (random numbers
+    drawn by the caller).  Raises if the search enters more than
+    ``node_limit`` cells."""
+    c = _square(n, cells)
+    vo = None
+    if value_order is not None:
+        vo = np.ascontiguousarray(np.asarray(value_order, dtype=np.uint8).reshape(n * n, n))
+    out = np.full(n * n, EMPTY, dtype=np.uint8)
+    r = _load().oracle_first(n, int(bool(vs)), _u8(c), None if vo is None else _u8(vo), node_limit, _u8(out))
+    if r < 0:
+        raise ValueError("invalid oracle input or node limit reached")
+    return out if r == 1 else None
 
 
 def assignments(n: int, base, cells: Sequence[int], vs: bool = False) -> np.ndarray:

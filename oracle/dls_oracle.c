@@ -170,6 +170,67 @@ int64_t oracle_count(int n, int vs, const uint8_t *cells)
     return result;
 }
 
+/* ---- one completion: the same nested loops, stopping at the first square.
+ * Used to build complete squares of larger orders as test inputs (the
+ * near-complete prefixes that pin the counts of orders 11-16).  Value k of
+ * cell c is tried in the order given by value_order[c*n + k] (a permutation
+ * of 0..n-1 per cell, drawn by the caller; NULL = 0..n-1). */
+
+typedef struct {
+    or_state st;
+    const uint8_t *value_order;
+    int64_t nodes, limit;
+} or_first;
+
+static int or_first_rec(or_first *f, int k)
+{
+    or_state *s = &f->st;
+    if (k == s->norder) return 1;
+    if (++f->nodes > f->limit) return -1;
+    int n = s->n;
+    int c = s->order[k], i = c / n, j = c % n;
+    for (int t = 0; t < n; t++) {
+        int v = f->value_order ? f->value_order[c * n + t] : t;
+        if (!or_allowed(s, i, j, v)) continue;
+        or_mark(s, i, j, v, 1);
+        int r = or_first_rec(f, k + 1);
+        if (r) return r;                 /* found (cells stay marked) or limit */
+        or_mark(s, i, j, v, 0);
+    }
+    return 0;
+}
+
+/* 1: out (n*n) holds a square agreeing with cells; 0: none exists;
+ * -1: invalid arguments or more than node_limit cells entered. */
+int oracle_first(int n, int vs, const uint8_t *cells, const uint8_t *value_order,
+                 int64_t node_limit, uint8_t *out)
+{
+    if (!or_check_args(n, cells)) return -1;
+    if (value_order)
+        for (int c = 0; c < n * n; c++) {
+            int seen = 0;
+            for (int t = 0; t < n; t++) {
+                int v = value_order[c * n + t];
+                if (v >= n || (seen >> v) & 1) return -1;
+                seen |= 1 << v;
+            }
+        }
+    or_first *f = (or_first *)malloc(sizeof(or_first));
+    if (!f) return -1;
+    f->value_order = value_order;
+    f->nodes = 0;
+    f->limit = node_limit;
+    int r = 0;
+    if (or_load(&f->st, n, vs, cells)) {
+        or_make_order(&f->st);
+        r = or_first_rec(f, 0);
+        if (r == 1)
+            for (int c = 0; c < n * n; c++) out[c] = (uint8_t)f->st.ls[c / n][c % n];
+    }
+    free(f);
+    return r;
+}
+
 /* ---- many prefixes on a pool of threads (independent subproblems, Sec. 5.2) */
 
 typedef struct {

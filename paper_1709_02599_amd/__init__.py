@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "DLS_VSYM", "DLS_SYMBREAK", "DLS_PLAIN", "DLS_EMPTY", "DLSError", "LIB_PATH",
     "dls_version", "dls_strerror", "dls_last_hip_error", "dls_order", "dls_split", "dls_split_from",
-    "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async",
+    "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async", "dls_stream_status",
     "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
     "dls_count_cells_async", "dls_split_cells", "dls_order_cost",
@@ -81,8 +81,8 @@ def _load() -> ctypes.CDLL:
         "dls_canon": (ctypes.c_int, [ctypes.c_int, u8p, u32p]),
         "dls_count": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_uint64)]),
-        "dls_count_async": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp, ctypes.c_int64,
-                                           vp, vp, vp]),
+        "dls_count_async": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, vp, ctypes.c_int64, vp, vp]),
+        "dls_stream_status": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint32)]),
         "dls_count_async_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp,
                                               ctypes.c_int64, vp, vp, vp,
                                               ctypes.POINTER(DlsLaunch)]),
@@ -248,12 +248,19 @@ def _launch(launch) -> Optional[DlsLaunch]:
     return DlsLaunch(**launch)
 
 
-def dls_count_async(n: int, flags: int, pattern, d_prefixes, num: int, d_counts,
-                    d_status=None, stream=None) -> None:
-    pat = _pattern(n, pattern)
-    _check(_lib.dls_count_async(n, flags, None if pat is None else _u8(pat), _ptr(d_prefixes),
-                                num, _ptr(d_counts), _ptr(d_status), _stream(stream)),
+def dls_count_async(n: int, flags: int, d_prefixes, num: int, d_counts, stream=None) -> None:
+    """Counts of device prefixes into device counts on `stream`; the pattern
+    of assigned cells is read from prefix 0."""
+    _check(_lib.dls_count_async(n, flags, _ptr(d_prefixes), num, _ptr(d_counts), _stream(stream)),
            "dls_count_async")
+
+
+def dls_stream_status(stream=None) -> int:
+    """Status bits of the calls made on `stream` without a status buffer
+    (waits for the stream; clears them)."""
+    v = ctypes.c_uint32(0)
+    _check(_lib.dls_stream_status(_stream(stream), ctypes.byref(v)), "dls_stream_status")
+    return int(v.value)
 
 
 def dls_count_async_ex(n: int, flags: int, pattern, d_prefixes, num: int, d_counts,

@@ -96,6 +96,14 @@ struct QueueSlot {
     uint64_t *tcounts = nullptr;
     size_t ebuf_bytes = 0;
     int64_t ecap = 0;
+    // status word used when the caller passes no d_status (read and cleared by
+    // dls_stream_status)
+    uint32_t *status = nullptr;
+    // set once work on this stream has been captured into a graph: the graph
+    // keeps this slot's buffer addresses, so a buffer outgrown later is
+    // retired (kept until the process ends) instead of freed
+    bool pinned = false;
+    std::vector<void *> retired;
 };
 
 constexpr size_t kMaxTimed = 1 << 16;
@@ -163,16 +171,24 @@ int queue_slot(DeviceState *ds, void *stream, size_t records_bytes, QueueSlot **
         if (hipMalloc((void **)&s.ctrl, sizeof(dlsk::Ctrl)) != hipSuccess) return DLS_ENOMEM;
         if (hipMalloc(&s.items, kMaxRecord * kItemCap) != hipSuccess) return DLS_ENOMEM;
         if (hipMalloc((void **)&s.ready, sizeof(uint32_t) * kItemCap) != hipSuccess) return DLS_ENOMEM;
+        if (hipMalloc((void **)&s.status, sizeof(uint32_t)) != hipSuccess) return DLS_ENOMEM;
         s.cap = kItemCap;
         hipError_t e2 = hipMemset(s.ctrl, 0, sizeof(dlsk::Ctrl));
         if (e2 == hipSuccess) e2 = hipMemset(s.ready, 0, sizeof(uint32_t) * kItemCap);
+        if (e2 == hipSuccess) e2 = hipMemset(s.status, 0, sizeof(uint32_t));
         if (e2 == hipSuccess) e2 = hipDeviceSynchronize();
         if (e2 != hipSuccess) return hip_fail(e2, DLS_EDEVICE);
         it = ds->slots.emplace(stream, s).first;
     }
     QueueSlot &q = it->second;
+    if (cap) q.pinned = true;
     if (q.records_bytes < records_bytes) {
-        if (q.records) {
+        if (q.records && q.pinned) {
+            // a captured graph may still use it
+            q.retired.push_back(q.records);
+            q.records = nullptr;
+            q.records_bytes = 0;
+        } else if (q.records) {
             // the previous batch on this stream may still be running
             hipError_t e3 = hipStreamSynchronize((hipStream_t)stream);
             if (e3 != hipSuccess) return hip_fail(e3, DLS_EDEVICE);
@@ -195,11 +211,16 @@ int expand_buffers(void *stream, QueueSlot *q, int64_t ecap, size_t rb) {
     if (q->ex && q->ecap >= ecap && q->ebuf_bytes >= want) return DLS_OK;
     if (capturing(stream)) return DLS_ECAPTURE;
     if (q->ex) {
-        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+        if (!q->pinned) {
+            hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+        }
         for (void *p : {(void *)q->ebuf[0], (void *)q->ebuf[1], (void *)q->eorig[0], (void *)q->eorig[1],
                         (void *)q->tcounts})
-            if (p) (void)hipFree(p);
+            if (p) {
+                if (q->pinned) q->retired.push_back(p);  // a captured graph may still use it
+                else (void)hipFree(p);
+            }
         q->ebuf[0] = q->ebuf[1] = nullptr;
         q->eorig[0] = q->eorig[1] = nullptr;
         q->tcounts = nullptr;
@@ -313,6 +334,7 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     rc = queue_slot(ds, stream, dlsk::record_bytes(n, vs) * (size_t)num, &qs);
     if (rc) return rc;
     a.records = qs->records;
+    if (!a.status) a.status = qs->status;  // reported by dls_stream_status
     if (launch && launch->time_kernel) {
         if (capturing(stream)) return DLS_ECAPTURE;
         std::lock_guard<std::mutex> lk(g_dev_mu);
@@ -645,9 +667,45 @@ int dls_canon(int n, const uint8_t *h, uint32_t *mult_out) {
     return DLS_OK;
 }
 
-int dls_count_async(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,
-                    uint64_t *d_counts, uint32_t *d_status, void *stream) {
-    return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, nullptr, nullptr);
+int dls_count_async(int n, uint32_t flags, const uint8_t *d_prefixes, int64_t num, uint64_t *d_counts,
+                    void *stream) {
+    if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
+    if (num > 0 && (!d_prefixes || !d_counts)) return DLS_EINVAL;
+    if (num == 0) return DLS_OK;
+    // the pattern of assigned cells is prefix 0's: one small copy on the
+    // caller's stream, which waits for the work queued there before it
+    if (capturing(stream)) return DLS_ECAPTURE;
+    uint8_t first[DLS_MAXN * DLS_MAXN];
+    hipError_t e = hipMemcpyAsync(first, d_prefixes, (size_t)n * n, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+    if (!valid_cells(n, first)) return DLS_EINVAL;
+    const std::vector<uint8_t> pat = pattern_of(n, first);
+    return count_async_impl(n, flags, pat.data(), d_prefixes, num, d_counts, nullptr, stream, nullptr, nullptr);
+}
+
+int dls_stream_status(void *stream, uint32_t *status_out) {
+    if (!status_out) return DLS_EINVAL;
+    DeviceState *ds = nullptr;
+    int dev = 0;
+    int rc = device_state(&ds, &dev);
+    if (rc) return rc;
+    uint32_t *word = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        auto it = ds->slots.find(stream);
+        if (it != ds->slots.end()) word = it->second.status;
+    }
+    *status_out = 0;
+    if (!word) return DLS_OK;  // nothing was ever counted on this stream
+    if (capturing(stream)) return DLS_ECAPTURE;
+    uint32_t v = 0;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipMemcpy(&v, word, sizeof(v), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && v) e = hipMemset(word, 0, sizeof(v));
+    if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+    *status_out = v;
+    return DLS_OK;
 }
 
 int dls_count_async_ex(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,

@@ -161,3 +161,37 @@ def test_host_order_cost_equals_device_step_count(order7):
         order = dls.dls_order_variant(7, 0, pattern, v)
         host_steps, _ = dls.dls_order_cost(7, 0, order, pre)
         assert st == 0 and steps == 2 * host_steps, v
+
+
+def test_captured_graph_survives_a_larger_eager_batch_on_its_stream(order7):
+    # A captured step keeps the addresses of its stream's scratch; a later
+    # uncaptured call on the same stream with a larger batch must not free
+    # them (the library retires outgrown buffers of captured streams).
+    import torch
+    from paper_1709_02599_amd.graphs import CountStep
+    pre, want = order7
+    dev = torch.device("cuda:0")
+    small = pre[:300].copy()
+    d_pre = torch.from_numpy(small).to(dev)
+    d_cnt = torch.zeros(len(small), dtype=torch.int64, device=dev)
+    d_st = torch.zeros(1, dtype=torch.int32, device=dev)
+    pattern = (small[0] != E).astype(np.uint8)
+    step = CountStep(7, 0, pattern, d_pre, len(small), d_cnt, d_st,
+                     launch=dls.DlsLaunch(expand_target=4096)).capture()
+    big_pre, _ = dls.dls_split(7, 0, 11)
+    big_want = oracle.count_many(7, big_pre)
+    d_big = torch.from_numpy(big_pre).to(dev)
+    for rep in range(3):
+        # larger batch, larger expansion target: both outgrow the captured buffers
+        d_bc = torch.zeros(len(big_pre), dtype=torch.int64, device=dev)
+        dls.dls_count_async_ex(7, 0, (big_pre[0] != E).astype(np.uint8), d_big, len(big_pre), d_bc, None,
+                               step.stream, dls.DlsLaunch(expand_target=8192 << rep))
+        step.stream.synchronize()
+        assert dls.dls_stream_status(step.stream) == 0
+        assert np.array_equal(d_bc.cpu().numpy().view(np.uint64), big_want)
+        d_cnt.fill_(-1)
+        torch.cuda.synchronize()
+        step.replay()
+        torch.cuda.synchronize()
+        assert int(d_st.item()) == 0
+        assert np.array_equal(d_cnt.cpu().numpy().view(np.uint64), want[:300]), f"replay {rep}"

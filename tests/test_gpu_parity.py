@@ -188,11 +188,13 @@ def order8_symbreak():
     omult = np.concatenate(mults)
     a = np.lexsort(pre.T[::-1])
     b = np.lexsort(opre.T[::-1])
-    return pre, mult, opre, omult, a, b
+    # every workunit counted by the oracle (seconds on the host's threads)
+    ocounts = oracle.count_many(n, opre)
+    return pre, mult, opre, omult, a, b, ocounts
 
 
 def test_order8_symbreak_prefix_lists_agree(order8_symbreak):
-    pre, mult, opre, omult, a, b = order8_symbreak
+    pre, mult, opre, omult, a, b, _ = order8_symbreak
     assert pre.shape == opre.shape
     assert np.array_equal(pre[a], opre[b])
     assert np.array_equal(mult[a], omult[b])
@@ -200,15 +202,24 @@ def test_order8_symbreak_prefix_lists_agree(order8_symbreak):
 
 @pytest.mark.parametrize("plain", KERNELS)
 def test_order8_symbreak_counts(order8_symbreak, plain):
-    pre, mult, opre, omult, a, b = order8_symbreak
+    pre, mult, opre, omult, a, b, ocounts = order8_symbreak
     c, st = gpu_counts(dls, 8, 0, pre, plain=plain)
     assert st == 0
     # Corollary 1: sum of class power x count is the fixed-first-row total
     assert weighted_total(c, mult) == golden_io.counts()[(8, "fixed")]
-    # sampled prefixes counted one by one by the oracle
-    pos = workloads.sample_positions(len(pre), 1500, seed=8)
-    oc = oracle.count_many(8, opre[b[pos]])
-    assert np.array_equal(c[a[pos]], oc)
+    # all 2 819 311 workunits, element by element against the oracle
+    assert np.array_equal(c[a], ocounts[b])
+
+
+def test_order8_symbreak_tuned_launch_counts(order8_symbreak):
+    # the launch the benchmark times (fill-order variant 5, VGPR masks,
+    # 16 workgroups of 256 per CU, refill every 64 steps, chunks >= 16)
+    pre, mult, opre, omult, a, b, ocounts = order8_symbreak
+    launch = {"block": 256, "blocks_per_cu": 16, "refill_every": 64, "order_variant": 5,
+              "chunk_min": 16, "lds_masks": -1}
+    c, st = gpu_counts(dls, 8, 0, pre, launch=launch)
+    assert st == 0
+    assert np.array_equal(c[a], ocounts[b])
 
 
 def test_order8_symbreak_kernels_agree_everywhere(order8_symbreak):
@@ -233,8 +244,26 @@ def test_vs_order8_full_count(plain):
     c, st = gpu_counts(dls, n, dls.DLS_VSYM, pre, plain=plain)
     assert st == 0
     assert int(c.sum()) == oracle.count(n, oracle.identity_prefix(n), vs=True)
-    pos = workloads.sample_positions(len(pre), 400, seed=81)
-    assert np.array_equal(c[pos], oracle.count_many(n, opre[pos], vs=True))
+    # all 114 960 workunits, element by element
+    assert np.array_equal(c, oracle.count_many(n, opre, vs=True))
+
+
+def test_order8_full_count_without_symmetry_breaking():
+    # the sustained workload: the 14 diagonal cells split on the host
+    # (547 896 workunits), every one of the 7 447 587 840 squares with the
+    # first row fixed (Sec. 5.1); 2 000 seeded workunits element by element
+    n = 8
+    pre, _ = dls.dls_split(n, 0, 14)
+    assert len(pre) == 547_896
+    opre = _oracle_split(n, False, 14)
+    assert np.array_equal(pre, opre)
+    pos = workloads.sample_positions(len(pre), 2000, seed=14)
+    want = oracle.count_many(n, opre[pos])
+    for launch in (None, {"order_variant": 1}):
+        c, st = gpu_counts(dls, n, 0, pre, launch=launch)
+        assert st == 0
+        assert int(c.sum()) == golden_io.counts()[(8, "fixed")]
+        assert np.array_equal(c[pos], want), launch
 
 
 def test_vs_odd_order_is_zero():
@@ -274,6 +303,44 @@ def test_inconsistent_prefixes_and_ragged_tail(plain):
     assert np.all(c[::7] == 0)
 
 
+@pytest.mark.parametrize("flags", [0, dls.DLS_PLAIN])
+def test_count_async_six_arguments(flags):
+    # the scope-table form: device prefixes and counts on a stream, pattern
+    # read from prefix 0, status kept by the library per stream
+    import torch
+    n = 7
+    pre, _ = dls.dls_split(n, 0, 11)
+    want = oracle.count_many(n, oracle.assignments(n, oracle.identity_prefix(n), oracle.fill_order(n)[:11]))
+    st = torch.cuda.Stream()
+    d_pre = torch.from_numpy(pre).cuda()
+    d_cnt = torch.full((len(pre),), -1, dtype=torch.int64, device="cuda")
+    dls.dls_count_async(n, flags, d_pre, len(pre), d_cnt, st)
+    assert dls.dls_stream_status(st) == 0
+    assert np.array_equal(d_cnt.cpu().numpy().view(np.uint64), want)
+    # a prefix with another pattern counts 0 and is reported on the stream
+    bad = pre[:16].copy()
+    bad[5, n * n - 1] = 3
+    d_bad = torch.from_numpy(bad).cuda()
+    d_c2 = torch.zeros(16, dtype=torch.int64, device="cuda")
+    dls.dls_count_async(n, flags, d_bad, 16, d_c2, st)
+    assert dls.dls_stream_status(st) & 1
+    got = d_c2.cpu().numpy().view(np.uint64)
+    assert got[5] == 0 and np.array_equal(np.delete(got, 5), np.delete(want[:16], 5))
+    assert dls.dls_stream_status(st) == 0          # read clears the word
+
+
+def test_count_async_vs_six_arguments():
+    import torch
+    pre, _ = dls.dls_split(8, dls.DLS_VSYM, 10)
+    sel = pre[workloads.sample_positions(len(pre), 200, seed=11)]
+    d_pre = torch.from_numpy(sel).cuda()
+    d_cnt = torch.zeros(len(sel), dtype=torch.int64, device="cuda")
+    s = torch.cuda.current_stream()
+    dls.dls_count_async(8, dls.DLS_VSYM, d_pre, len(sel), d_cnt, s)
+    assert dls.dls_stream_status(s) == 0
+    assert np.array_equal(d_cnt.cpu().numpy().view(np.uint64), oracle.count_many(8, sel, vs=True))
+
+
 def test_pattern_mismatch_flagged():
     pre, _ = dls.dls_split(6, 0, 4)
     pre = pre[:10].copy()
@@ -286,7 +353,7 @@ def test_pattern_mismatch_flagged():
 def test_empty_batch():
     import torch
     d = torch.zeros(1, dtype=torch.int64, device="cuda")
-    dls.dls_count_async(6, 0, None, d, 0, d)      # nothing to do
+    dls.dls_count_async(6, 0, d, 0, d)            # nothing to do
     torch.cuda.synchronize()
     assert dls.dls_count(6, 0, np.zeros((0, 36), np.uint8)).shape == (0,)
 
@@ -385,12 +452,11 @@ def test_lds_masks_order7_split_and_donation(block):
 
 
 def test_lds_masks_order8_symbreak(order8_symbreak):
-    pre, mult, opre, omult, a, b = order8_symbreak
+    pre, mult, opre, omult, a, b, ocounts = order8_symbreak
     c1, s1 = gpu_counts(dls, 8, 0, pre, launch=LDS_MASKS)
     c2, s2 = gpu_counts(dls, 8, 0, pre, launch={**LDS_MASKS, "block": 512, "order_variant": 5})
-    c0, s0 = gpu_counts(dls, 8, 0, pre)
-    assert s0 == s1 == s2 == 0
-    assert np.array_equal(c1, c0) and np.array_equal(c2, c0)
+    assert s1 == s2 == 0
+    assert np.array_equal(c1[a], ocounts[b]) and np.array_equal(c2[a], ocounts[b])
     assert weighted_total(c1, mult) == golden_io.counts()[(8, "fixed")]
 
 

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 from tests import golden_io
+import dls_workloads as workloads
 
 E = oracle.EMPTY
 
@@ -440,3 +441,54 @@ def test_split_set_independent_of_order(n, vs, k):
     sa = sorted(map(bytes, a))
     assert sa == sorted(map(bytes, b))
     assert int(oracle.count_many(n, a, vs=vs).sum()) == oracle.count(n, base, vs=vs)
+
+
+# --------------------------------------------------------------------------
+# one completion (builds the complete squares of orders 11-16 used as test
+# inputs); pinned by the definition (Sec. 1) and against the counts
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,vs", [(n, False) for n in range(1, 17)] + [(n, True) for n in (2, 4, 6, 8, 10, 12, 14, 16)])
+def test_first_completion_is_a_square_agreeing_with_the_prefix(n, vs):
+    rng = workloads.SplitMix64(1000 + n)
+    vo = workloads.random_permutations(n, n * n, rng)
+    sq = oracle.first_completion(n, oracle.identity_prefix(n), vo, vs=vs)
+    if n in (2, 3) or (vs and n == 2):
+        assert sq is None                          # no DLS of order 2 or 3
+        return
+    assert sq is not None
+    assert oracle.is_dls(n, sq, vs=vs)
+    assert np.array_equal(sq[:n], np.arange(n))
+
+
+@pytest.mark.parametrize("n,vs", [(4, False), (5, False), (6, False), (4, True), (6, True)])
+def test_first_completion_exists_exactly_when_the_count_is_positive(n, vs):
+    rng = workloads.SplitMix64(77 + n)
+    for trial in range(40):
+        p = workloads.random_prefix(n, 2 + rng.below(2 * n), vs, rng)
+        vo = workloads.random_permutations(n, n * n, rng)
+        sq = oracle.first_completion(n, p, vo, vs=vs)
+        cnt = oracle.count(n, p, vs=vs)
+        assert (sq is not None) == (cnt > 0), (trial, cnt)
+        if sq is not None:
+            assert oracle.is_dls(n, sq, vs=vs)
+            keep = p != 0xFF
+            assert np.array_equal(sq[keep], p[keep])
+
+
+def test_first_completion_rejects_a_bad_value_order():
+    vo = np.tile(np.arange(5, dtype=np.uint8), (25, 1))
+    vo[3, 1] = 0                                   # not a permutation
+    with pytest.raises(ValueError):
+        oracle.first_completion(5, oracle.identity_prefix(5), vo)
+
+
+@pytest.mark.parametrize("n,vs", [(11, False), (12, True), (13, False), (16, True)])
+def test_blanked_square_counts_at_least_one(n, vs):
+    # a complete square with cells emptied has the square itself among its
+    # completions; emptying all but row 0 of a small order gives the full count
+    rng = workloads.SplitMix64(5 * n + vs)
+    sq = oracle.first_completion(n, oracle.identity_prefix(n), workloads.random_permutations(n, n * n, rng), vs=vs)
+    p = workloads.blank_cells(n, sq, 24, vs, rng)
+    assert int((p == 0xFF).sum()) == (48 if vs else 24)
+    assert oracle.count(n, p, vs=vs) >= 1
