@@ -85,6 +85,18 @@ def launch_of(dls, settings, time_kernel=0):
     return dls.DlsLaunch(time_kernel=time_kernel, **kw)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,7 +160,7 @@ def main():
     d_mult = torch.from_numpy(mult.astype(np.int32)).to(dev)   # class powers < 2^31
     d_cnt = torch.zeros(num, dtype=torch.int64, device=dev)
     d_status = torch.zeros(1, dtype=torch.int32, device=dev)
-    d_steps = torch.zeros(1, dtype=torch.int64, device=dev)
+    d_steps = torch.zeros(2, dtype=torch.int64, device=dev)   # DFS steps, executed lane-steps
     d_total = torch.zeros(1, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     tuned = tuned_launch(8, 0, "order8-symbreak-row1")
@@ -157,11 +169,23 @@ def main():
         dls.dls_count_async_ex(n, flags, pattern, d_pre, num, d_cnt, d_status, stream, launch)
         dls.dls_reduce_weighted(d_cnt, d_mult, num, d_total, stream)
 
-    # deterministic work measure: DFS steps of the whole batch (instrumented run)
+    # the plain kernel at the persistent leg's fill order and workgroup size
+    # (equal work), and at the library defaults (reported separately)
+    plain_same = {k: tuned[k] for k in ("order_variant", "block") if k in tuned}
+
+    # deterministic work measure: DFS steps of the whole batch (instrumented
+    # run), and the lane-steps each kernel executes (parked lanes included)
     dls.dls_count_async_stats(n, 0, pattern, d_pre, num, d_cnt, d_status, stream,
                               launch_of(dls, tuned), d_steps)
     torch.cuda.synchronize()
-    total_steps = int(d_steps.item())
+    total_steps = int(d_steps[0].item())
+    lane_steps = {"persistent": int(d_steps[1].item())}
+    d_steps.zero_()
+    dls.dls_count_async_stats(n, dls.DLS_PLAIN, pattern, d_pre, num, d_cnt, d_status, stream,
+                              launch_of(dls, plain_same), d_steps)
+    torch.cuda.synchronize()
+    plain_dfs_steps = int(d_steps[0].item())          # equals total_steps: same order, same tree
+    lane_steps["plain"] = int(d_steps[1].item())
     leaves = int(d_cnt.sum().item())
     weighted = int((d_cnt * d_mult).sum().item())
     assert weighted == ORDER8_FIXED, weighted
@@ -173,7 +197,12 @@ def main():
         for _ in range(8):
             run(0, launch_of(dls, tuned))
         for _ in range(3):
-            run(dls.DLS_PLAIN, launch_of(dls, {}))
+            run(dls.DLS_PLAIN, launch_of(dls, plain_same))
+        # the integer-VALU probe (24 VALU instructions per iteration)
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        sink = torch.zeros(cus * 8 * 256, dtype=torch.int32, device=dev)
+        for _ in range(3):
+            dls.dls_valu_probe(cus * 8, 20000, sink, stream)
         src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device=dev).fill_(1)
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -188,7 +217,8 @@ def main():
     # reduction of the weighted total; the library records a HIP event pair
     # around every search kernel on this stream.
     results = {}
-    for name, flags, settings in (("persistent", 0, tuned), ("plain", dls.DLS_PLAIN, {})):
+    for name, flags, settings in (("persistent", 0, tuned), ("plain", dls.DLS_PLAIN, plain_same),
+                                  ("plain_defaults", dls.DLS_PLAIN, {})):
         for _ in range(args.warmup):
             run(flags, launch_of(dls, settings))
         torch.cuda.synchronize()
@@ -243,7 +273,9 @@ def main():
     tuned7 = tuned_launch(7, 0, "order7-diag11")
     reps7 = 50
     order7 = {"prefixes": len(pre7), "launch": tuned7 or "library defaults"}
-    for name, flags, settings in (("persistent", 0, tuned7), ("plain", dls.DLS_PLAIN, {})):
+    plain7 = {k: tuned7[k] for k in ("order_variant", "block") if k in tuned7}
+    order7["plain_launch"] = plain7 or "library defaults"
+    for name, flags, settings in (("persistent", 0, tuned7), ("plain", dls.DLS_PLAIN, plain7)):
         dls.dls_count_async_ex(7, flags, pat7, d7, len(pre7), c7, d_status, stream, launch_of(dls, settings))
         torch.cuda.synchronize()
         timed7 = launch_of(dls, settings, time_kernel=1)
@@ -278,7 +310,9 @@ def main():
         sd_cnt = torch.zeros(len(spre), dtype=torch.int64, device=dev)
         stuned = tuned_launch(n, 0, "order8-diag14")
         sustained = {"prefixes": len(spre), "leaves": ORDER8_FIXED, "launch": stuned or "library defaults"}
-        for name, flags, settings in (("persistent", 0, stuned), ("plain", dls.DLS_PLAIN, {})):
+        splain = {k: stuned[k] for k in ("order_variant", "block") if k in stuned}
+        sustained["plain_launch"] = splain or "library defaults"
+        for name, flags, settings in (("persistent", 0, stuned), ("plain", dls.DLS_PLAIN, splain)):
             lc = launch_of(dls, settings)
             dls.dls_count_async_ex(n, flags, spat, sd_pre, len(spre), sd_cnt, d_status, stream, lc)
             torch.cuda.synchronize()
@@ -385,11 +419,19 @@ def main():
             if dt > args.cpu_seconds / 3 or k >= len(reps):
                 break
             k = min(len(reps), int(k * min(20.0, args.cpu_seconds / max(dt, 1e-3))))
+        # one thread on a smaller slice of the same sample (context for the
+        # paper's per-core rates of Table 1)
+        one = spl[workloads.sample_positions(len(spl), max(1, len(spl) // max(1, threads)), seed=3)]
+        t1 = time.perf_counter()
+        o1 = oracle.count_many(n, one, threads=1)
+        dt1 = time.perf_counter() - t1
         cpu = {"value": float(oc.sum()) / dt, "unit": "DLS/s", "cores": threads, "kind": "oracle",
                "sample": f"{k} seeded canonical hourglasses of {len(reps)} with all row-1 "
                          f"fillings ({len(spl)} prefixes, {int(oc.sum())} squares), "
                          f"{dt:.1f} s on {threads} threads",
-               "seconds": dt}
+               "seconds": dt, "cpu_model": cpu_model(),
+               "single_thread": {"value": float(o1.sum()) / dt1, "unit": "DLS/s", "prefixes": len(one),
+                                 "squares": int(o1.sum()), "seconds": dt1}}
 
     p = results["persistent"]
     value = leaves / (p["ms_per_step"] * 1e-3)
@@ -419,14 +461,23 @@ def main():
         "cpu_baseline": cpu,
         "plain_kernel": {"value": leaves / (results["plain"]["ms_per_step"] * 1e-3),
                          "ms_per_step": results["plain"]["ms_per_step"],
-                         "kernel_ms": results["plain"]["kernel_ms"]},
+                         "kernel_ms": results["plain"]["kernel_ms"],
+                         "launch": plain_same or "library defaults",
+                         "dfs_steps": plain_dfs_steps,
+                         "useful_lane_steps": plain_dfs_steps / lane_steps["plain"]},
+        "plain_kernel_defaults": {"value": leaves / (results["plain_defaults"]["ms_per_step"] * 1e-3),
+                                  "ms_per_step": results["plain_defaults"]["ms_per_step"],
+                                  "kernel_ms": results["plain_defaults"]["kernel_ms"],
+                                  "launch": "library defaults (workgroup 256, the order of Sec. 2.3)"},
         "persistent_kernel_ms": p["kernel_ms"],
+        "persistent_useful_lane_steps": total_steps / lane_steps["persistent"],
         "graph": graph,
         "order7_diag_split": order7,
         "vs_order10_full": vs10,
         "order6_single_prefix": order6,
         "order8_symbreak_end_to_end": end_to_end,
         "speedup_persistent_vs_plain": results["plain"]["ms_per_step"] / p["ms_per_step"],
+        "speedup_persistent_vs_plain_defaults": results["plain_defaults"]["ms_per_step"] / p["ms_per_step"],
         "effective_counted_per_s": weighted / (p["ms_per_step"] * 1e-3),
         "dfs_steps_per_launch": total_steps,
         "alg_ops_per_launch": alg_ops,

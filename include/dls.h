@@ -297,11 +297,14 @@ int dls_count_async_ex(int n, uint32_t flags, const uint8_t *pattern, const uint
                        int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream,
                        const dls_launch *launch);
 
-/* As dls_count_async_ex; in addition, when d_steps != NULL, the number of
- * DFS steps taken by all lanes is added into *d_steps (device uint64).  A
- * step either enters a cell with a candidate value or returns from a cell
- * whose candidates are exhausted; the count feeds the operation-count model
- * behind the roofline figures. */
+/* As dls_count_async_ex; in addition, when d_steps != NULL (device
+ * uint64[2]): d_steps[0] += the number of DFS steps taken by all lanes, and
+ * d_steps[1] += the number of steps the lanes executed, including the steps
+ * of lanes without work that run along with their wave (so d_steps[0] /
+ * d_steps[1] is the share of useful lane-steps).  A DFS step either enters a
+ * cell with a candidate value or returns from a cell whose candidates are
+ * exhausted; the count is the same for every launch shape and feeds the
+ * operation-count model behind the roofline figures. */
 int dls_count_async_stats(int n, uint32_t flags, const uint8_t *pattern,
                           const uint8_t *d_prefixes, int64_t num, uint64_t *d_counts,
                           uint32_t *d_status, void *stream, const dls_launch *launch,

@@ -444,12 +444,30 @@ struct LdsLane {
 };
 
 // Lane state of the persistent kernel with the line masks in VGPRs (packed
-// 64-bit words as in Lane) and 8-byte level descriptors in LDS:
+// 64-bit words as in Lane) and level descriptors in LDS.
+//
+// Even N <= 8 without vertical symmetry (no cell lies on both diagonals;
+// one 64-bit word per kind of line): 16-byte descriptors {row shift, column
+// shift, diagonal shift, leaf increment}.  Both diagonal masks live in one
+// word D: main diagonal in bits 0-7, antidiagonal in bits 8-15, bits 16-23
+// zero and bits 24-31 all ones.  The diagonal shift is 0 or 8 for a cell on
+// the main or the antidiagonal, 48 for a cell on neither: marking uses the
+// low word of a 64-bit shift (nothing, for 48), reading a 32-bit shift,
+// which takes the shift modulo 32 (the zero field, for 48).  One level past
+// the last (the sentinel) has shift 56: nothing to mark, and it reads the
+// all-ones field, so a lane that steps onto it has no candidates and goes
+// back up; its increment is 1, so every square is counted by the step that
+// reaches the sentinel (two extra steps per square instead of a popcount and
+// a leaf test in every step).
+//
+// Otherwise: 8-byte descriptors
 //   x = row shift | row word << 6 | (on main diagonal ? ALL << 16 : 0)
-//   y = column shift | column word << 6 | (on antidiagonal ? ALL << 16 : 0)
+//   y = column shift | column word << 6 | keep << 8 | (on antidiagonal ? ALL << 16 : 0)
 // The 64-bit shifts read only the low 6 bits of x / y, and the diagonal
 // masks are kept in bits 16-31 (mdh, adh), so a diagonal test is one AND
-// with x or y: no field extraction in the search loop.
+// with x or y: no field extraction in the search loop.  keep (N <= 8):
+// AllN, and 0 at the last level, whose candidates are counted instead of
+// entered.
 constexpr uint32_t kVlStackBase = 8u * kMaxLevels;
 
 __host__ __device__ inline uint32_t vl_stacks_end(int nlev, int block, int elem) {
@@ -457,95 +475,148 @@ __host__ __device__ inline uint32_t vl_stacks_end(int nlev, int block, int elem)
     return (end + 15u) & ~15u;
 }
 
+// diagonal shifts of the D form
+constexpr uint32_t kDwNone = 48u;      // on neither diagonal
+constexpr uint32_t kDwSentinel = 56u;  // the level past the last
+
+template <int N, bool VS>
+struct VLaneDesc {
+    // D word form: even order, no vertical symmetry, 8-bit lines
+    static constexpr bool DW = (N % 2 == 0) && !VS && N <= 8;
+    static constexpr uint32_t DB = DW ? 16u : 8u;      // descriptor bytes
+    static constexpr uint32_t DSH = DW ? 4u : 3u;
+    using T = typename std::conditional<DW, uint4, uint2>::type;
+    // stack rows and descriptors a plan of nlev levels needs (D form: one
+    // more, the sentinel)
+    __host__ __device__ static int rows(int nlev) { return DW ? nlev + 1 : nlev; }
+    __device__ __forceinline__ static T load(uint32_t a) {
+        if constexpr (DW) return lds_ld4(a);
+        else return lds_ld2(a);
+    }
+};
+// the 16-byte descriptor table spans 128 levels, more than any order <= 8 has
+static_assert(16u * 128u <= kVlStackBase, "descriptor table overlaps the stacks");
+
 template <int N, bool VS>
 struct VLane {
     using G = Geo<N, VS>;
+    using DT = VLaneDesc<N, VS>;
+    using Desc = typename DT::T;
+    static constexpr bool DW = DT::DW;
+    static constexpr uint32_t DB = DT::DB;
     uint64_t R[G::WR];  // row lines
     uint64_t C[G::WC];  // column lines (left half only with VS)
-    uint32_t mdh, adh;  // diagonal masks << 16
+    uint32_t mdh, adh;  // diagonal masks << 16 (D form: the word D in mdh)
     uint32_t cand;      // remaining candidates at the current level
-    uint2 cur;          // descriptor of the current level's cell
-    uint32_t da;        // LDS address of the current level's descriptor (base + 8 * level)
+    Desc cur;           // descriptor of the current level's cell
+    uint32_t da;        // LDS address of the current level's descriptor (base + DB * level)
     uint32_t da0;       // the same for the level at which this task began
     uint32_t sa;        // LDS address of this lane's stack entry for the current level
     uint32_t c32;       // squares completed since the last flush()
     uint64_t cnt;       // squares completed by this task (after flush())
 
-    __device__ __forceinline__ int depth(uint32_t dbase) const { return (int)((da - dbase) >> 3); }
-    __device__ __forceinline__ int start_level(uint32_t dbase) const { return (int)((da0 - dbase) >> 3); }
+    __device__ __forceinline__ int depth(uint32_t dbase) const { return (int)((da - dbase) >> DT::DSH); }
+    __device__ __forceinline__ int start_level(uint32_t dbase) const { return (int)((da0 - dbase) >> DT::DSH); }
     __device__ __forceinline__ void flush() {
         cnt += c32;
         c32 = 0u;
     }
     __device__ __forceinline__ bool done() const { return cand == 0u && da == da0; }
 
-    __device__ __forceinline__ uint32_t cands(const uint2 &d) const {
-        const uint32_t r = (uint32_t)(pickw<G::WR>(R, (d.x >> 6) & 3u) >> (d.x & 63u));
-        const uint32_t c = (uint32_t)(pickw<G::WC>(C, (d.y >> 6) & 3u) >> (d.y & 63u));
-        return G::ALL & ~(r | c | (((mdh & d.x) | (adh & d.y)) >> 16));
+    // all lines of the cell of d: row | column | diagonals (bits above N undefined)
+    __device__ __forceinline__ uint32_t lines(const Desc &d) const {
+        if constexpr (DW) {
+            return (uint32_t)(R[0] >> d.x) | (uint32_t)(C[0] >> d.y) | (mdh >> (d.z & 31u));
+        } else {
+            const uint32_t r = (uint32_t)(pickw<G::WR>(R, (d.x >> 6) & 3u) >> (d.x & 63u));
+            const uint32_t c = (uint32_t)(pickw<G::WC>(C, (d.y >> 6) & 3u) >> (d.y & 63u));
+            return r | c | (((mdh & d.x) | (adh & d.y)) >> 16);
+        }
     }
+    __device__ __forceinline__ uint32_t cands(const Desc &d) const { return G::ALL & ~lines(d); }
 
     // mark or clear (XOR) the value bit b at the cell of descriptor d
-    __device__ __forceinline__ void toggle(const uint2 &d, uint32_t b) {
-        const uint32_t bh = b << 16;
-        if constexpr (VS) {
-            const uint32_t rb = (1u << (N - 1)) >> (__builtin_ctz(b) & 31u);  // N-1-v
-            const uint32_t rbh = rb << 16;
-            flipw<G::WR>(R, (d.x >> 6) & 3u, (uint64_t)(b | rb) << (d.x & 63u));
-            flipw<G::WC>(C, (d.y >> 6) & 3u, (uint64_t)b << (d.y & 63u));
-            mdh ^= (bh & d.x) | (rbh & d.y);
-            adh ^= (bh & d.y) | (rbh & d.x);
+    __device__ __forceinline__ void toggle(const Desc &d, uint32_t b) {
+        if constexpr (DW) {
+            R[0] ^= (uint64_t)b << d.x;
+            C[0] ^= (uint64_t)b << d.y;
+            mdh ^= (uint32_t)((uint64_t)b << d.z);  // nothing for a shift >= 32
         } else {
-            flipw<G::WR>(R, (d.x >> 6) & 3u, (uint64_t)b << (d.x & 63u));
-            flipw<G::WC>(C, (d.y >> 6) & 3u, (uint64_t)b << (d.y & 63u));
-            mdh ^= bh & d.x;
-            adh ^= bh & d.y;
+            const uint32_t bh = b << 16;
+            if constexpr (VS) {
+                const uint32_t rb = (1u << (N - 1)) >> (__builtin_ctz(b) & 31u);  // N-1-v
+                const uint32_t rbh = rb << 16;
+                flipw<G::WR>(R, (d.x >> 6) & 3u, (uint64_t)(b | rb) << (d.x & 63u));
+                flipw<G::WC>(C, (d.y >> 6) & 3u, (uint64_t)b << (d.y & 63u));
+                mdh ^= (bh & d.x) | (rbh & d.y);
+                adh ^= (bh & d.y) | (rbh & d.x);
+            } else {
+                flipw<G::WR>(R, (d.x >> 6) & 3u, (uint64_t)b << (d.x & 63u));
+                flipw<G::WC>(C, (d.y >> 6) & 3u, (uint64_t)b << (d.y & 63u));
+                mdh ^= bh & d.x;
+                adh ^= bh & d.y;
+            }
         }
     }
 
     // One DFS step, taken by every lane of the wave (see LdsLane::step for
-    // the parked lanes).  nsa = nda * kst + sc0 (kst = stride / 8).  Up to
-    // N = 8 bits 8-15 of y hold a keep mask: AllN, and 0 at the last level,
-    // whose candidates are counted instead of entered; no lane is ever
-    // parked at the last level (see from_rec), so an up step never lands on
-    // it and needs no guard.
+    // the parked lanes).  nsa = nda * kst + sc0 (kst = stride / DB).  Up to
+    // N = 8 a keep mask is AllN, and 0 at the last level, whose candidates
+    // are counted instead of entered; no lane is ever parked at the last
+    // level (see from_rec), so an up step never lands on it and needs no
+    // guard.  The stack read at nsa serves up lanes (the slot they return
+    // to); a down lane reads the slot below it, which it does not use.
     template <class S>
     __device__ __forceinline__ void step(uint32_t kst, uint32_t sc0, uint32_t da_last) {
         const bool up = (cand == 0u);
-        const uint32_t nda = (uint32_t)max((int)(da + (up ? 0u - 8u : 8u)), (int)da0);
+        const uint32_t nda = (uint32_t)max((int)(da + (up ? 0u - DB : DB)), (int)da0);
         const uint32_t nsa = __umul24(nda, kst) + sc0;
-        const uint2 nd = lds_ld2(nda);
-        const uint32_t saved = lds_ld<S>(up ? nsa : sa);
+        const Desc nd = DT::load(nda);
+        const uint32_t saved = lds_ld<S>(nsa);
         lds_st<S>(sa, (S)cand);  // up lanes write 0 into a slot nobody reads again
         const uint32_t stored = up ? saved : cand;
         const uint32_t b = stored & (0u - stored);
         toggle(up ? nd : cur, b);
-        const uint32_t nc = cands(nd);
-        if constexpr (N <= 8) {
-            const uint32_t keep = (nd.y >> 8) & 0xFFu;
-            c32 += (uint32_t)__builtin_popcount(nc & ~keep);
-            cand = up ? (stored ^ b) : (nc & keep);
+        if constexpr (DW) {
+            // a square is counted on reaching the sentinel (increment 1);
+            // both candidate sets are formed and one is kept by a mask, so
+            // the step stays one branch-free instruction stream
+            c32 += nd.w;
+            const uint32_t upm = 0u - (uint32_t)up;
+            cand = ((stored ^ b) & upm) | (G::ALL & ~lines(nd) & ~upm);
         } else {
-            const bool leaf = (nda == da_last) && !up;
-            c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
-            cand = up ? (stored ^ b) : (leaf ? 0u : nc);
+            const uint32_t nc = cands(nd);
+            if constexpr (N <= 8) {
+                const uint32_t keep = (nd.y >> 8) & 0xFFu;
+                c32 += (uint32_t)__builtin_popcount(nc & ~keep);
+                cand = up ? (stored ^ b) : (nc & keep);
+            } else {
+                const bool leaf = (nda == da_last) && !up;
+                c32 += leaf ? (uint32_t)__builtin_popcount(nc) : 0u;
+                cand = up ? (stored ^ b) : (leaf ? 0u : nc);
+            }
         }
         cur = nd;
         da = nda;
         sa = nsa;
     }
 
-    // Start the task of record r (dbase: LDS address of the 8-byte
-    // descriptor table; lane_off / stride: this lane's level-0 stack entry
-    // and the distance between levels).
+    // Start the task of record r (dbase: LDS address of the descriptor
+    // table; lane_off / stride: this lane's level-0 stack entry and the
+    // distance between levels).
     __device__ __forceinline__ void from_rec(const Rec<N, VS> &r, uint32_t dbase, int last, uint32_t lane_off,
                                              uint32_t stride) {
 #pragma unroll
         for (int k = 0; k < G::WR; ++k) R[k] = r.R[k];
 #pragma unroll
         for (int k = 0; k < G::WC; ++k) C[k] = r.C[k];
-        mdh = r.diag << 16;
-        adh = r.diag & 0xFFFF0000u;
+        if constexpr (DW) {
+            mdh = (r.diag & 0xFFu) | ((r.diag >> 8) & 0xFF00u) | (G::ALL << 24);
+            adh = 0u;
+        } else {
+            mdh = r.diag << 16;
+            adh = r.diag & 0xFFFF0000u;
+        }
         cnt = 0;
         c32 = 0u;
         const uint32_t lvl = r.cl >> 16;
@@ -553,7 +624,7 @@ struct VLane {
             cand = 0u;
             da = da0 = dbase;
             sa = lane_off;
-            cur = lds_ld2(dbase);
+            cur = DT::load(dbase);
             return;
         }
         cand = r.cl & 0xFFFFu;
@@ -563,9 +634,9 @@ struct VLane {
             cand = 0u;
             at = lvl - 1u;  // parked one level up (the plan has at least two levels)
         }
-        da = da0 = dbase + 8u * at;
+        da = da0 = dbase + DB * at;
         sa = lane_off + at * stride;
-        cur = lds_ld2(da);
+        cur = DT::load(da);
     }
 
     // Give away the untried siblings at level lvl: the record holds the
@@ -577,7 +648,7 @@ struct VLane {
         VLane T = *this;
         for (int l = depth(dbase) - 1; l >= lvl; --l) {
             const uint32_t sv = *slot_of(l);
-            T.toggle(lds_ld2(dbase + 8u * (uint32_t)l), sv & (0u - sv));
+            T.toggle(DT::load(dbase + DB * (uint32_t)l), sv & (0u - sv));
         }
         const uint32_t sv = *slot_of(lvl);
         const uint32_t b = sv & (0u - sv);
@@ -586,7 +657,8 @@ struct VLane {
         for (int k = 0; k < G::WR; ++k) r.R[k] = T.R[k];
 #pragma unroll
         for (int k = 0; k < G::WC; ++k) r.C[k] = T.C[k];
-        r.diag = (T.mdh >> 16) | (T.adh & 0xFFFF0000u);
+        if constexpr (DW) r.diag = (T.mdh & 0xFFu) | ((T.mdh & 0xFF00u) << 8);
+        else r.diag = (T.mdh >> 16) | (T.adh & 0xFFFF0000u);
         r.cl = (sv ^ b) | ((uint32_t)lvl << 16);
         r.origin = origin;
         r.pad = 0;
@@ -595,17 +667,26 @@ struct VLane {
     }
 };
 
-// 8-byte descriptor table of VLane from the plan
+// descriptor table of VLane from the plan
 template <int N, bool VS>
 __device__ __forceinline__ void vl_build_desc(const Plan &plan, unsigned char *smem) {
     using G = Geo<N, VS>;
-    uint2 *t = reinterpret_cast<uint2 *>(smem);
     for (int k = threadIdx.x; k < plan.nlev; k += blockDim.x) {
         const uint32_t d = plan.desc[k];
         // keep mask (N <= 8): AllN except at the last level
-        const uint32_t keep = (N <= 8 && k != plan.nlev - 1) ? (G::ALL << 8) : 0u;
-        t[k] = make_uint2((d & 0xFFu) | ((d_md(d) & G::ALL) << 16),
-                          ((d >> 8) & 0xFFu) | keep | ((d_ad(d) & G::ALL) << 16));
+        const uint32_t keep = (N <= 8 && k != plan.nlev - 1) ? G::ALL : 0u;
+        if constexpr (VLaneDesc<N, VS>::DW) {
+            // one word per kind of line: the shifts are the bit offsets
+            const uint32_t z = (d >> 16) & 1u ? 0u : ((d >> 17) & 1u ? 8u : kDwNone);
+            reinterpret_cast<uint4 *>(smem)[k] = make_uint4(d & 63u, (d >> 8) & 63u, z, 0u);
+        } else {
+            reinterpret_cast<uint2 *>(smem)[k] =
+                make_uint2((d & 0xFFu) | ((d_md(d) & G::ALL) << 16),
+                           ((d >> 8) & 0xFFu) | (keep << 8) | ((d_ad(d) & G::ALL) << 16));
+        }
+    }
+    if constexpr (VLaneDesc<N, VS>::DW) {
+        if (threadIdx.x == 0) reinterpret_cast<uint4 *>(smem)[plan.nlev] = make_uint4(0u, 0u, kDwSentinel, 1u);
     }
 }
 
@@ -759,27 +840,41 @@ __global__ void __launch_bounds__(1024) plain_kernel(const Plan plan, const Rec<
     __syncthreads();
 
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= num) return;
-    const Rec<N, VS> r = recs[idx];
-    if ((r.cl >> 16) == kNone) return;  // result already written by the prep kernel
-    const uint32_t dbase = lds_of(smem);
-    const uint32_t lane_off = dbase + kStackBase + threadIdx.x * (uint32_t)sizeof(S);
-    const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
-    const uint32_t da_last = dbase + 4u * (uint32_t)(nlev - 1);
-    Lane<N, VS> L;
-    L.from_rec(r, sdesc, nlev - 1, dbase, lane_off, stride);
     uint64_t nsteps = 0;
-    // the 32-bit step counter is folded into the 64-bit count every 256 steps
-    for (;;) {
-        for (int k = 0; k < 256 && !L.done(); ++k) {
-            L.template step<S>(stride, da_last);
-            if (STATS) ++nsteps;
+    // a dead or complete prefix: result already written by the prep kernel
+    const bool live = idx < num && (recs[idx < num ? idx : 0].cl >> 16) != kNone;
+    if (live) {
+        const Rec<N, VS> r = recs[idx];
+        const uint32_t dbase = lds_of(smem);
+        const uint32_t lane_off = dbase + kStackBase + threadIdx.x * (uint32_t)sizeof(S);
+        const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
+        const uint32_t da_last = dbase + 4u * (uint32_t)(nlev - 1);
+        Lane<N, VS> L;
+        L.from_rec(r, sdesc, nlev - 1, dbase, lane_off, stride);
+        // the 32-bit step counter is folded into the 64-bit count every 256 steps
+        for (;;) {
+            for (int k = 0; k < 256 && !L.done(); ++k) {
+                L.template step<S>(stride, da_last);
+                if (STATS) ++nsteps;
+            }
+            L.flush();
+            if (L.done()) break;
         }
-        L.flush();
-        if (L.done()) break;
+        counts[idx] = L.cnt;
     }
-    counts[idx] = L.cnt;
-    if (STATS && steps) atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
+    if (STATS && steps) {
+        if (live) atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
+        // a wave issues as many steps as its longest lane takes (every lane of
+        // the wave takes part in the shuffles: none has returned)
+        uint64_t wmax = nsteps;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t y = ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(wmax >> 32), o) << 32) |
+                               (uint32_t)__shfl_xor((int)(uint32_t)wmax, o);
+            wmax = y > wmax ? y : wmax;
+        }
+        if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)(steps + 1), (unsigned long long)(wmax * 64u));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -824,9 +919,8 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v, int src) {
 // s_memrealtime ticks at 100 MHz: 20 s without any queue progress ends the kernel
 constexpr uint64_t kStallTicks = 100000000ull * 20;
 
-// s_waitcnt immediate for gfx9: vmcnt <= 1 (bits 3:0 and 15:14), no wait on
+// s_waitcnt immediate for gfx9: vmcnt = 0 (bits 3:0 and 15:14), no wait on
 // expcnt (bits 6:4 = 7) or lgkmcnt (bits 11:8 = 15)
-constexpr int kWaitVm1 = 0x0F71;
 constexpr int kWaitVm0 = 0x0F70;
 
 template <int N, bool VS, bool STATS, bool LM>
@@ -877,9 +971,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     L.cand = 0u;
     L.da = L.da0 = dbase;
     L.sa = lane_off;
-    L.cur = make_uint2(0u, 0u);
+    L.cur = {};
     // stack address from descriptor address (see VLane::step, LdsLane::step)
-    constexpr uint32_t kDescBytes = LM ? LdsLane<N, VS>::DB : 8u;
+    constexpr uint32_t kDescBytes = LM ? LdsLane<N, VS>::DB : VLane<N, VS>::DB;
     const uint32_t kst = stride / kDescBytes;
     const uint32_t sc0 = lane_off - dbase * kst;
     lds_st<S>(lane_off, (S)0);  // the parked start slot of a lane without a task
@@ -887,6 +981,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     L.c32 = 0u;
     if constexpr (LM) L.mbase = dbase + lm_desc_bytes(nlev, VS) + threadIdx.x * 4u;
     const uint32_t da_last = dbase + kDescBytes * (uint32_t)last;
+    constexpr bool DSENT = !LM && VLaneDesc<N, VS>::DW;
     bool has = false;           // lane holds a task (possibly finished)
     uint64_t *out = &ctrl->sink;  // where this lane's task count goes (a sink until the first task)
     // start the task of a record / give away part of this lane's task
@@ -907,7 +1002,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     uint64_t stored = 0;        // part of L.cnt already in *out
     bool static_left = true;    // wave-uniform
     uint64_t cb = 0, ce = 0;    // wave-private range of static tasks
-    uint64_t nsteps = 0;
+    uint64_t nsteps = 0, nexec = 0;  // DFS steps; steps executed by the lane, parked or not
     uint64_t seen_sig = ~0ull, seen_at = 0;
     uint32_t backoff = 1, tick = 0;
     bool asked = false;         // this (idle poller) wave is counted in ctrl->hungry
@@ -921,7 +1016,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             for (int it = 0; it < tune.refill_every; it += 2) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    if (STATS) nsteps += (has && !L.done()) ? 1u : 0u;
+                    // the steps onto and off the sentinel (D form) are not DFS steps
+                    if (STATS) {
+                        nsteps += (has && !L.done() && !(DSENT && (L.da == da_last + kDescBytes ||
+                                                                  (L.da == da_last && L.cand)))) ? 1u : 0u;
+                        ++nexec;
+                    }
                     L.template step<S>(kst, sc0, da_last);
                 }
             }
@@ -933,13 +1033,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
         if (static_left) {
             // ------------- retire + refill from the static queue -------------
             // While static tasks remain no lane gives work away, so each count
-            // has a single writer: the lane stores its running count (the last
-            // store is the final one) instead of adding atomically.  Tasks come
-            // from a wave-private range refilled with a guided chunk
+            // has a single writer: a lane whose task finished stores its count
+            // (no atomics).  A task still running when the static list runs
+            // out has stored nothing; it adds its count atomically when it
+            // finishes in the tail (prep zeroed the slot).  Tasks come from a
+            // wave-private range refilled with a guided chunk
             // (remaining / (2 * waves), at least chunk_min) by one atomic on
-            // ctrl->head.  Every lane issues the same memory operations (one
-            // record load, then one count store), so the wait below covers
-            // the loads only.
+            // ctrl->head.
             if (want && ((int)__popcll(want) >= tune.refill_min || want == ~0ull)) {
                 const bool idle = !has || fin;
                 const uint64_t k = (uint64_t)__popcll(want);
@@ -971,10 +1071,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                 }
                 const Rec<N, VS> r = recs[my_id >= 0 ? my_id : 0];
                 asm volatile("" ::: "memory");  // keep the load ahead of the store
-                *out = L.cnt;
-                stored = L.cnt;
-                __builtin_amdgcn_s_waitcnt(kWaitVm1);
-                if (fin) has = false;
+                if (fin) {
+                    *out = L.cnt;
+                    has = false;
+                }
                 if (my_id >= 0) {
                     start(r);
                     out = &counts[r.origin];
@@ -1029,7 +1129,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                     got = shfl_words(r, src);
                 } else {
                     // through the wave's LDS mailbox (cheaper in registers)
-                    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(smem + vl_stacks_end(nlev, blockDim.x, sizeof(S))) +
+                    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(
+                                           smem + vl_stacks_end(VLaneDesc<N, VS>::rows(nlev), blockDim.x, sizeof(S))) +
                                        (threadIdx.x & ~63u);
                     if (lvl >= 0 && drank < m) mbox[drank] = give(lvl);
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -1188,7 +1289,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
         // that the search loop never waits on one
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }
-    if (STATS && steps) atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
+    if (STATS && steps) {
+        atomicAdd((unsigned long long *)steps, (unsigned long long)nsteps);
+        atomicAdd((unsigned long long *)(steps + 1), (unsigned long long)nexec);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1235,15 +1339,31 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, o);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), o);
-        x += ((uint64_t)hi << 32) | lo;
-    }
+// 64-bit value of lane (this lane's DPP source) added to x; lanes outside
+// row_mask add 0
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_add64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK, 0xF, false);
+    return x + (((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the wave by DPP lane moves: swaps within pairs and quads, the
+// half-row and row mirrors (every lane of a 16-lane row then holds the row's
+// sum), then the row broadcasts of lanes 15 and 31 into the rows above.  The
+// total ends in lane 63.  Every lane of the wave must be active.
+__device__ __forceinline__ uint64_t wave_sum64_last(uint64_t x) {
+    x = dpp_add64<0xB1>(x);         // quad_perm [1,0,3,2]
+    x = dpp_add64<0x4E>(x);         // quad_perm [2,3,0,1]
+    x = dpp_add64<0x141>(x);        // row_half_mirror
+    x = dpp_add64<0x140>(x);        // row_mirror
+    x = dpp_add64<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x = dpp_add64<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
     return x;
 }
+
+// the same total in every lane
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) { return bcast64(wave_sum64_last(x), 63); }
 
 // Inclusive sum over the workgroup (W waves of 64 lanes); *total gets the
 // workgroup's sum.  Uses part[W] of LDS; every thread must call it.
@@ -1617,17 +1737,27 @@ __global__ void zero_one(uint64_t *out) {
 __global__ void __launch_bounds__(256) reduce_weighted(const uint64_t *__restrict__ counts,
                                                        const uint32_t *__restrict__ mult, int64_t num,
                                                        uint64_t *out) {
-    __shared__ uint64_t part[256];
+    // four counts per thread and step: two 16-byte count loads and one
+    // 16-byte weight load when both arrays are 16-byte aligned
+    const bool vec = ((uintptr_t)counts % 16 == 0) && ((uintptr_t)mult % 16 == 0);
+    const int64_t nv = vec ? num / 4 : 0;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     uint64_t acc = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < num; k += (int64_t)gridDim.x * blockDim.x)
-        acc += counts[k] * (mult ? (uint64_t)mult[k] : 1ull);
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
-        __syncthreads();
+    for (int64_t q = t0; q < nv; q += nt) {
+        const ulonglong2 c0 = reinterpret_cast<const ulonglong2 *>(counts)[2 * q];
+        const ulonglong2 c1 = reinterpret_cast<const ulonglong2 *>(counts)[2 * q + 1];
+        if (mult) {
+            const uint4 m = reinterpret_cast<const uint4 *>(mult)[q];
+            acc += c0.x * m.x + c0.y * m.y + c1.x * m.z + c1.y * m.w;
+        } else {
+            acc += c0.x + c0.y + c1.x + c1.y;
+        }
     }
-    if (threadIdx.x == 0 && part[0]) atomicAdd((unsigned long long *)out, (unsigned long long)part[0]);
+    for (int64_t k = 4 * nv + t0; k < num; k += nt) acc += counts[k] * (mult ? (uint64_t)mult[k] : 1ull);
+    // one atomic per wave
+    acc = wave_sum64_last(acc);
+    if ((threadIdx.x & 63) == 63 && acc) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
 }
 
 // integer VALU probe: 8 independent dependency chains of 32-bit xor/add/shift per lane
@@ -1770,7 +1900,8 @@ size_t lds_bytes(int n, bool vs, int nlev, int block, bool persistent, bool lds_
         const int lines = n >= kLmPackMinN ? n : n + (vs ? (n + 1) / 2 : n);  // LdsLane<n, vs>::LINES
         return lm_stacks_end(lines, nlev, block, elem, vs);
     }
-    return vl_stacks_end(nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
+    const bool dw = n % 2 == 0 && !vs && n <= 8;  // VLaneDesc<n, vs>::DW: one more level, the sentinel
+    return vl_stacks_end(dw ? nlev + 1 : nlev, block, elem) + record_bytes(n, vs) * (size_t)block;
 }
 
 hipError_t launch_zero(uint64_t *p, int64_t n, hipStream_t stream) {
@@ -1786,7 +1917,9 @@ hipError_t launch_reduce_weighted(const uint64_t *counts, const uint32_t *mult, 
     (void)hipGetLastError();
     hipLaunchKernelGGL(zero_one, dim3(1), dim3(64), 0, stream, out);
     if (num > 0) {
-        const unsigned grid = (unsigned)((num + 255) / 256 < 2048 ? (num + 255) / 256 : 2048);
+        // one thread per four counts, at most 4096 workgroups of 256
+        const int64_t want = (num / 4 + 255) / 256 + 1;
+        const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
         hipLaunchKernelGGL(reduce_weighted, dim3(grid), dim3(256), 0, stream, counts, mult, num, out);
     }
     return hipGetLastError();

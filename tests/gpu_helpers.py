@@ -15,7 +15,7 @@ def gpu_counts(dls, n, flags, prefixes, plain=False, launch=None, stream=None, s
     d_pre = torch.from_numpy(pre).to(dev)
     d_cnt = torch.zeros(max(1, num), dtype=torch.int64, device=dev)
     d_status = torch.zeros(1, dtype=torch.int32, device=dev)
-    d_steps = torch.zeros(1, dtype=torch.int64, device=dev)
+    d_steps = torch.zeros(2, dtype=torch.int64, device=dev)
     pattern = (pre[0] != EMPTY).astype(np.uint8) if num else None
     fl = flags | (dls.DLS_PLAIN if plain else 0)
     st = stream if stream is not None else torch.cuda.current_stream()
@@ -27,7 +27,7 @@ def gpu_counts(dls, n, flags, prefixes, plain=False, launch=None, stream=None, s
     counts = d_cnt.cpu().numpy().view(np.uint64)[:num].copy()
     status = int(d_status.item())
     if steps:
-        return counts, status, int(d_steps.item())
+        return counts, status, int(d_steps[0].item())
     return counts, status
 
 

@@ -195,3 +195,31 @@ def test_captured_graph_survives_a_larger_eager_batch_on_its_stream(order7):
         torch.cuda.synchronize()
         assert int(d_st.item()) == 0
         assert np.array_equal(d_cnt.cpu().numpy().view(np.uint64), want[:300]), f"replay {rep}"
+
+
+def test_host_order_cost_equals_device_step_count_order8():
+    # order 8 runs the two-word diagonal form with a sentinel level past the
+    # last; its steps onto and off the sentinel are not DFS steps
+    import torch
+    import dls_workloads as workloads
+    pre, _ = dls.dls_split(8, 0, 12)
+    pre = pre[workloads.sample_positions(len(pre), 3000, seed=12)]
+    pattern = (pre[0] != E).astype(np.uint8)
+    want = oracle.count_many(8, pre)
+    dev = torch.device("cuda:0")
+    d_pre = torch.from_numpy(pre).to(dev)
+    for v in (0, 5):
+        order = dls.dls_order_variant(8, 0, pattern, v)
+        host_steps, leaves = dls.dls_order_cost(8, 0, order, pre)
+        assert leaves == int(want.sum())
+        for launch in ({"order_variant": v, "expand_target": -1},
+                       {"order_variant": v, "expand_target": -1, "steal_depth": 6, "refill_every": 8}):
+            d_cnt = torch.zeros(len(pre), dtype=torch.int64, device=dev)
+            d_st = torch.zeros(1, dtype=torch.int32, device=dev)
+            d_steps = torch.zeros(2, dtype=torch.int64, device=dev)
+            dls.dls_count_async_stats(8, 0, pattern, d_pre, len(pre), d_cnt, d_st, None, launch, d_steps)
+            torch.cuda.synchronize()
+            assert int(d_st.item()) == 0
+            assert np.array_equal(d_cnt.cpu().numpy().view(np.uint64), want), launch
+            assert int(d_steps[0].item()) == 2 * host_steps, launch
+            assert int(d_steps[1].item()) >= int(d_steps[0].item())

@@ -319,7 +319,8 @@ def test_count_async_six_arguments(flags):
     assert np.array_equal(d_cnt.cpu().numpy().view(np.uint64), want)
     # a prefix with another pattern counts 0 and is reported on the stream
     bad = pre[:16].copy()
-    bad[5, n * n - 1] = 3
+    free = int(np.flatnonzero(pre[0] == E)[-1])    # a cell no prefix assigns
+    bad[5, free] = 3
     d_bad = torch.from_numpy(bad).cuda()
     d_c2 = torch.zeros(16, dtype=torch.int64, device="cuda")
     dls.dls_count_async(n, flags, d_bad, 16, d_c2, st)
