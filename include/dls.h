@@ -237,6 +237,9 @@ typedef struct {
                            line to mark a value) instead of packed VGPR
                            words; negative = VGPR layout; 0 = library
                            default (LDS from order 9 on)                 */
+    int refill_min;     /* persistent kernel: while static tasks remain, a
+                           wave refills its idle lanes when at least this
+                           many are idle (1..64; 0 = default 8)           */
 } dls_launch;
 
 /*

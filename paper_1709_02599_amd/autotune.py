@@ -5,8 +5,9 @@ counting launch on the GPU under every combination of
 
 * fill-order variant (`dls_order_variant`: the Sec. 2.3 rule and variants of
   its weights and tie-breaks; the order changes the work, never the count),
-* workgroup size, and
-* refill cadence (DFS steps between queue visits),
+* workgroup size,
+* refill cadence (DFS steps between queue visits) and trigger (idle lanes
+  that make a wave refill), grid size, smallest static chunk, mask layout,
 
 checks that every candidate returns the same counts (tuning cannot change a
 result), and keeps the fastest.  `tune_depth` does the same over split
@@ -28,7 +29,9 @@ import numpy as np
 
 from . import (DLS_PLAIN, DLS_SYMBREAK, DlsLaunch, dls_count_async_ex, dls_kernel_time_ms, dls_split)
 
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+# DLS_AUTOTUNE_CACHE overrides the cache file (e.g. to tune into a scratch copy)
+CACHE = os.environ.get("DLS_AUTOTUNE_CACHE") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                              "autotune_cache.json")
 VARIANTS = tuple(range(8))
 BLOCKS = (128, 256, 512)
 REFILLS = (16, 32, 64)
@@ -69,7 +72,7 @@ def best(n: int, flags: int, workload: str, arch: Optional[str] = None) -> Optio
 
 
 FIELDS = ("block", "blocks_per_cu", "steal_depth", "refill_every", "order_variant", "time_kernel",
-          "expand_target", "chunk_min", "lds_masks")
+          "expand_target", "chunk_min", "lds_masks", "refill_min")
 
 
 def _launch(settings: dict, time_kernel: int = 0) -> DlsLaunch:
@@ -201,11 +204,18 @@ def main(argv=None):
                  default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1}, save=False)
         first = {k: v for k, v in r["best"].items() if k != "ms"}
         # stage 2: grid size (1x to 4x the resident default; waves beyond
-        # the resident ones only shrink the guided chunks) and smallest chunk
+        # the resident ones only shrink the guided chunks), smallest chunk and
+        # the number of idle lanes that triggers a refill
         d = 2048 // first["block"]
         r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
                  space={**{k: (v,) for k, v in first.items()}, "blocks_per_cu": (0, d * 2, d * 3, d * 4),
-                        "chunk_min": (0, 4, 16, 64)},
+                        "chunk_min": (0, 4, 16, 64), "refill_min": (1, 2, 4, 8, 16)},
+                 default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1}, save=False)
+        second = {k: v for k, v in r["best"].items() if k != "ms"}
+        # stage 3: refill cadence against the refill trigger
+        r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
+                 space={**{k: (v,) for k, v in second.items() if k not in ("refill_every", "refill_min")},
+                        "refill_every": (16, 32, 64, 128), "refill_min": (1, 2, 4, 8, 16, 32)},
                  default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1})
         print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
                           "plain_ms": r["plain_ms"]}), flush=True)
@@ -224,8 +234,11 @@ def main(argv=None):
                           "top": r["table"][:6]}), flush=True)
     if want("order8-diag14"):
         spre, _ = dls_split(8, 0, 14)
-        s = tune(8, 0, spre, "order8-diag14", space={"order_variant": (0, 1, 2, 3, 5, 6)},
-                 default={"order_variant": 0}, reps=1)
+        s = tune(8, 0, spre, "order8-diag14",
+                 space={"order_variant": (0, 1, 5), "refill_every": (32, 64), "blocks_per_cu": (0, 16),
+                        "refill_min": (4, 8), "chunk_min": (0, 16)},
+                 default={"order_variant": 0, "refill_every": 32, "blocks_per_cu": 0, "refill_min": 8,
+                          "chunk_min": 0}, reps=1)
         print(json.dumps({"workload": "order8-diag14", "best": s["best"], "default": s["default"]}), flush=True)
 
     if want("order9-sample"):

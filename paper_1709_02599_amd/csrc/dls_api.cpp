@@ -330,8 +330,9 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     if (dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent, lm) > 64 * 1024) return DLS_EINVAL;
     a.tune.lds_masks = lm ? 1 : 0;
     a.block = block;
+    const size_t rb = dlsk::record_bytes(n, vs);
     QueueSlot *qs = nullptr;
-    rc = queue_slot(ds, stream, dlsk::record_bytes(n, vs) * (size_t)num, &qs);
+    rc = queue_slot(ds, stream, rb * (size_t)num, &qs);
     if (rc) return rc;
     a.records = qs->records;
     if (!a.status) a.status = qs->status;  // reported by dls_stream_status
@@ -374,7 +375,8 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
         int sd = (!expand && num < lanes / 4) ? std::max(8, a.plan.nlev / 3) : 0;
         if (launch && launch->steal_depth) sd = launch->steal_depth < 0 ? 0 : launch->steal_depth;
         a.tune.steal_depth = sd;
-        a.tune.refill_min = 8;
+        a.tune.refill_min = (launch && launch->refill_min) ? launch->refill_min : 8;
+        if (a.tune.refill_min < 1 || a.tune.refill_min > 64) return DLS_EINVAL;
         a.tune.donate_max = 2;
         a.tune.donate_low = 256;
         a.tune.tail_poll = 4;
@@ -382,7 +384,7 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
         if (a.tune.chunk_min < 1 || a.tune.chunk_min > 65536) return DLS_EINVAL;
         if (expand) {
             const int64_t ecap = 4 * et;
-            rc = expand_buffers(stream, qs, ecap, dlsk::record_bytes(n, vs));
+            rc = expand_buffers(stream, qs, ecap, rb);
             if (rc) return rc;
             a.ex = qs->ex;
             a.eblk = qs->eblk;

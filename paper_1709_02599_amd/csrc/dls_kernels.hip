@@ -1728,17 +1728,23 @@ __global__ void zero_u64(uint64_t *p, int64_t n) {
 }
 
 // out = sum_k mult[k] * counts[k] (mult == nullptr: all 1).  A first kernel
-// zeroes out; each workgroup of the second reduces its share in LDS and adds
-// it with one atomic.  Only kernels: the pair can be captured in a graph.
+// zeroes out; the second runs one workgroup of 1024 per CU over the array
+// (grid-stride, four counts per thread and step): each wave sums by DPP lane
+// moves, the workgroup's waves through LDS, and one atomic per workgroup adds
+// the result (atomics on one address are serialised, so their number is kept
+// to the number of CUs).  Only kernels: the pair can be captured in a graph.
 __global__ void zero_one(uint64_t *out) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *out = 0;
 }
 
-__global__ void __launch_bounds__(256) reduce_weighted(const uint64_t *__restrict__ counts,
-                                                       const uint32_t *__restrict__ mult, int64_t num,
-                                                       uint64_t *out) {
-    // four counts per thread and step: two 16-byte count loads and one
-    // 16-byte weight load when both arrays are 16-byte aligned
+constexpr int kReduceBlock = 1024;
+
+__global__ void __launch_bounds__(kReduceBlock) reduce_weighted(const uint64_t *__restrict__ counts,
+                                                                const uint32_t *__restrict__ mult, int64_t num,
+                                                                uint64_t *out) {
+    __shared__ uint64_t part[kReduceBlock / 64];
+    // two 16-byte count loads and one 16-byte weight load per step when both
+    // arrays are 16-byte aligned
     const bool vec = ((uintptr_t)counts % 16 == 0) && ((uintptr_t)mult % 16 == 0);
     const int64_t nv = vec ? num / 4 : 0;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1755,9 +1761,14 @@ __global__ void __launch_bounds__(256) reduce_weighted(const uint64_t *__restric
         }
     }
     for (int64_t k = 4 * nv + t0; k < num; k += nt) acc += counts[k] * (mult ? (uint64_t)mult[k] : 1ull);
-    // one atomic per wave
     acc = wave_sum64_last(acc);
-    if ((threadIdx.x & 63) == 63 && acc) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
+    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint64_t v = threadIdx.x < blockDim.x / 64 ? part[threadIdx.x] : 0ull;
+        v = wave_sum64_last(v);
+        if (threadIdx.x == 63 && v) atomicAdd((unsigned long long *)out, (unsigned long long)v);
+    }
 }
 
 // integer VALU probe: 8 independent dependency chains of 32-bit xor/add/shift per lane
@@ -1917,10 +1928,12 @@ hipError_t launch_reduce_weighted(const uint64_t *counts, const uint32_t *mult, 
     (void)hipGetLastError();
     hipLaunchKernelGGL(zero_one, dim3(1), dim3(64), 0, stream, out);
     if (num > 0) {
-        // one thread per four counts, at most 4096 workgroups of 256
-        const int64_t want = (num / 4 + 255) / 256 + 1;
-        const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
-        hipLaunchKernelGGL(reduce_weighted, dim3(grid), dim3(256), 0, stream, counts, mult, num, out);
+        // at most one workgroup per CU (a small array needs fewer)
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int64_t want = (num / 4 + kReduceBlock - 1) / kReduceBlock + 1;
+        const unsigned grid = (unsigned)(want < cus ? want : cus);
+        hipLaunchKernelGGL(reduce_weighted, dim3(grid), dim3(kReduceBlock), 0, stream, counts, mult, num, out);
     }
     return hipGetLastError();
 }
