@@ -300,6 +300,27 @@ int dls_count_async_ex(int n, uint32_t flags, const uint8_t *pattern, const uint
                        int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream,
                        const dls_launch *launch);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * count as dls_count_async_ex, with every scratch buffer (work-queue control
+ * block, donated-record slots, task records, expansion buffers) carved out
+ * of one static device array of 128 MiB that each GPU the library runs on
+ * holds until the process ends.  The call allocates nothing: no hipMalloc,
+ * no hipFree, no events.  The caller passes inputs, outputs and d_status
+ * (required: NULL gives DLS_EINVAL); launch->time_kernel is refused
+ * (DLS_EINVAL).  DLS_ERANGE if the batch's task records do not fit the array
+ * next to the fixed parts (about 4 million prefixes up to order 8, 32 bytes
+ * each; 80 bytes per prefix at order 16); the breadth-first expansion of
+ * small batches gets what is left, its target lowered to fit.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from several threads) race and give wrong counts;
+ * serialise them.  Each call clears what it needs cleared by kernels.
+ */
+int dls_count_async_noalloc(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes,
+                            int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream,
+                            const dls_launch *launch);
+
 /* As dls_count_async_ex; in addition, when d_steps != NULL (device
  * uint64[2]): d_steps[0] += the number of DFS steps taken by all lanes, and
  * d_steps[1] += the number of steps the lanes executed, including the steps

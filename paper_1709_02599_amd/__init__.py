@@ -19,7 +19,7 @@ __all__ = [
     "DLS_VSYM", "DLS_SYMBREAK", "DLS_PLAIN", "DLS_EMPTY", "DLSError", "LIB_PATH",
     "dls_version", "dls_strerror", "dls_last_hip_error", "dls_order", "dls_split", "dls_split_from",
     "dls_split_sample", "dls_group_order", "dls_canon", "dls_count", "dls_count_async", "dls_stream_status",
-    "dls_count_async_ex", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
+    "dls_count_async_ex", "dls_count_async_noalloc", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
     "dls_count_cells_async", "dls_split_cells", "dls_order_cost",
     "dls_hourglass_classes_async", "hourglass_classes_gpu",
@@ -87,6 +87,9 @@ def _load() -> ctypes.CDLL:
         "dls_count_async_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp,
                                               ctypes.c_int64, vp, vp, vp,
                                               ctypes.POINTER(DlsLaunch)]),
+        "dls_count_async_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp,
+                                                   ctypes.c_int64, vp, vp, vp,
+                                                   ctypes.POINTER(DlsLaunch)]),
         "dls_count_async_stats": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, vp,
                                                  ctypes.c_int64, vp, vp, vp,
                                                  ctypes.POINTER(DlsLaunch), vp]),
@@ -272,6 +275,18 @@ def dls_count_async_ex(n: int, flags: int, pattern, d_prefixes, num: int, d_coun
                                    num, _ptr(d_counts), _ptr(d_status), _stream(stream),
                                    None if lc is None else ctypes.byref(lc)),
            "dls_count_async_ex")
+
+
+def dls_count_async_noalloc(n: int, flags: int, pattern, d_prefixes, num: int, d_counts,
+                            d_status, stream=None, launch=None) -> None:
+    """dls_count_async_ex without any device allocation (scratch in the
+    library's static device array; overlapping calls on one GPU race)."""
+    pat = _pattern(n, pattern)
+    lc = _launch(launch)
+    _check(_lib.dls_count_async_noalloc(n, flags, None if pat is None else _u8(pat), _ptr(d_prefixes),
+                                        num, _ptr(d_counts), _ptr(d_status), _stream(stream),
+                                        None if lc is None else ctypes.byref(lc)),
+           "dls_count_async_noalloc")
 
 
 def dls_count_async_stats(n: int, flags: int, pattern, d_prefixes, num: int, d_counts,

@@ -120,9 +120,21 @@ struct CanonTables {
     int groups = 0, kcells = 0;
 };
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free entry point (dls_count_async_noalloc)
+// ---------------------------------------------------------------------------
+// One array per device, allocated with the code object and held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not the
+// device array: its device address comes from hipGetSymbolAddress, once per
+// device (DeviceState::scratch), and only that address reaches kernels.
+constexpr size_t kNoAllocBytes = size_t(128) << 20;
+constexpr int64_t kNoAllocItems = 1 << 14;  // donated-record slots
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 struct DeviceState {
     bool init = false;
     int cus = 0;
+    unsigned char *scratch = nullptr;   // device address of `scratch` on this device
     std::map<void *, QueueSlot> slots;  // scratch and work queue per stream
     std::map<int, CanonTables> canon;   // per order
 };
@@ -152,6 +164,10 @@ int device_state(DeviceState **out, int *dev_out) {
         hipError_t e1 = hipGetDeviceProperties(&prop, dev);
         if (e1 != hipSuccess) return hip_fail(e1, DLS_EDEVICE);
         ds.cus = prop.multiProcessorCount;
+        void *sp = nullptr;
+        hipError_t e2 = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+        if (e2 != hipSuccess) return hip_fail(e2, DLS_EDEVICE);
+        ds.scratch = static_cast<unsigned char *>(sp);
         ds.init = true;
     }
     *out = &ds;
@@ -288,9 +304,28 @@ int build_plan(int n, bool vs, const uint8_t *pattern, dlsk::Plan &plan, int var
     return DLS_OK;
 }
 
+// Carves the scratch of one call out of the static array: the work-queue
+// control block, the status word, the donated-record flags and slots (fixed
+// offsets, so that a call clears what the previous one left there), then the
+// task records and the expansion buffers.
+struct NoAllocLayout {
+    unsigned char *base;
+    size_t off = 0;
+    void *take(size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        void *p = base + off;
+        off += bytes;
+        return p;
+    }
+    size_t left() const {
+        const size_t at = (off + 255) & ~size_t(255);
+        return at < kNoAllocBytes ? kNoAllocBytes - at : 0;
+    }
+};
+
 int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes, int64_t num,
                      uint64_t *d_counts, uint32_t *d_status, void *stream, const dls_launch *launch,
-                     uint64_t *d_steps, const int *cells = nullptr, int ncells = 0) {
+                     uint64_t *d_steps, const int *cells = nullptr, int ncells = 0, bool noalloc = false) {
     if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
     if (num > 0 && (!d_prefixes || !d_counts)) return DLS_EINVAL;
     if (num == 0) return DLS_OK;
@@ -332,11 +367,24 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     a.block = block;
     const size_t rb = dlsk::record_bytes(n, vs);
     QueueSlot *qs = nullptr;
-    rc = queue_slot(ds, stream, rb * (size_t)num, &qs);
-    if (rc) return rc;
-    a.records = qs->records;
-    if (!a.status) a.status = qs->status;  // reported by dls_stream_status
+    NoAllocLayout na{ds->scratch};
+    if (noalloc) {
+        // nothing is allocated: every buffer is a piece of the static array
+        if (!ds->scratch) return DLS_EDEVICE;
+        a.ctrl = static_cast<dlsk::Ctrl *>(na.take(sizeof(dlsk::Ctrl)));
+        a.ready = static_cast<uint32_t *>(na.take(sizeof(uint32_t) * kNoAllocItems));
+        a.items = na.take(kMaxRecord * kNoAllocItems);
+        a.item_cap = kNoAllocItems;
+        if ((size_t)num > na.left() / rb) return DLS_ERANGE;
+        a.records = na.take(rb * (size_t)num);
+    } else {
+        rc = queue_slot(ds, stream, rb * (size_t)num, &qs);
+        if (rc) return rc;
+        a.records = qs->records;
+        if (!a.status) a.status = qs->status;  // reported by dls_stream_status
+    }
     if (launch && launch->time_kernel) {
+        if (noalloc) return DLS_EINVAL;  // the timing events would be allocated
         if (capturing(stream)) return DLS_ECAPTURE;
         std::lock_guard<std::mutex> lk(g_dev_mu);
         if (qs->ev_used == qs->ev.size()) {
@@ -352,10 +400,12 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
         ++qs->ev_used;
     }
     if (a.persistent) {
-        a.ctrl = qs->ctrl;
-        a.items = qs->items;
-        a.ready = qs->ready;
-        a.item_cap = qs->cap;
+        if (!noalloc) {
+            a.ctrl = qs->ctrl;
+            a.items = qs->items;
+            a.ready = qs->ready;
+            a.item_cap = qs->cap;
+        }
         int bpc = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 2048 / block;
         if (bpc < 1) bpc = 1;
         a.grid = ds->cus * bpc;
@@ -368,6 +418,14 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
         int64_t et = lanes;
         if (launch && launch->expand_target) et = launch->expand_target < 0 ? 0 : launch->expand_target;
         if (et > (1 << 28)) return DLS_EINVAL;
+        if (noalloc && et > num) {
+            // the expansion gets what is left of the array: 4 x target slots
+            // of two record buffers, two index arrays and one count array
+            const size_t fixed = 2 * sizeof(dlsk::Expand) + sizeof(uint32_t) * dlsk::kExBlocks + 6 * 256;
+            const size_t per = 4 * (2 * rb + 2 * sizeof(uint32_t) + sizeof(uint64_t));
+            const size_t fit = na.left() > fixed ? (na.left() - fixed) / per : 0;
+            if ((size_t)et > fit) et = (int64_t)fit;
+        }
         const bool expand = et > 0 && num < et && a.plan.nlev >= 3;
         // Global donation (work handed between waves through the device
         // queue) is for batches too small to keep the lanes busy that are not
@@ -384,15 +442,26 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
         if (a.tune.chunk_min < 1 || a.tune.chunk_min > 65536) return DLS_EINVAL;
         if (expand) {
             const int64_t ecap = 4 * et;
-            rc = expand_buffers(stream, qs, ecap, rb);
-            if (rc) return rc;
-            a.ex = qs->ex;
-            a.eblk = qs->eblk;
-            a.ebuf[0] = qs->ebuf[0];
-            a.ebuf[1] = qs->ebuf[1];
-            a.eorig[0] = qs->eorig[0];
-            a.eorig[1] = qs->eorig[1];
-            a.tcounts = qs->tcounts;
+            if (noalloc) {
+                a.ex = static_cast<dlsk::Expand *>(na.take(2 * sizeof(dlsk::Expand)));
+                a.eblk = static_cast<uint32_t *>(na.take(sizeof(uint32_t) * dlsk::kExBlocks));
+                a.ebuf[0] = na.take(rb * (size_t)ecap);
+                a.ebuf[1] = na.take(rb * (size_t)ecap);
+                a.eorig[0] = static_cast<uint32_t *>(na.take(sizeof(uint32_t) * (size_t)ecap));
+                a.eorig[1] = static_cast<uint32_t *>(na.take(sizeof(uint32_t) * (size_t)ecap));
+                a.tcounts = static_cast<uint64_t *>(na.take(sizeof(uint64_t) * (size_t)ecap));
+                if (na.off > kNoAllocBytes) return DLS_ERANGE;  // cannot happen: sized above
+            } else {
+                rc = expand_buffers(stream, qs, ecap, rb);
+                if (rc) return rc;
+                a.ex = qs->ex;
+                a.eblk = qs->eblk;
+                a.ebuf[0] = qs->ebuf[0];
+                a.ebuf[1] = qs->ebuf[1];
+                a.eorig[0] = qs->eorig[0];
+                a.eorig[1] = qs->eorig[1];
+                a.tcounts = qs->tcounts;
+            }
             a.ecap = ecap;
             a.etarget = et;
             a.epasses = std::min(a.plan.nlev - 2, 16);
@@ -684,6 +753,14 @@ int dls_count_async(int n, uint32_t flags, const uint8_t *d_prefixes, int64_t nu
     if (!valid_cells(n, first)) return DLS_EINVAL;
     const std::vector<uint8_t> pat = pattern_of(n, first);
     return count_async_impl(n, flags, pat.data(), d_prefixes, num, d_counts, nullptr, stream, nullptr, nullptr);
+}
+
+int dls_count_async_noalloc(int n, uint32_t flags, const uint8_t *pattern, const uint8_t *d_prefixes,
+                            int64_t num, uint64_t *d_counts, uint32_t *d_status, void *stream,
+                            const dls_launch *launch) {
+    if (num > 0 && !d_status) return DLS_EINVAL;
+    return count_async_impl(n, flags, pattern, d_prefixes, num, d_counts, d_status, stream, launch, nullptr,
+                            nullptr, 0, true);
 }
 
 int dls_stream_status(void *stream, uint32_t *status_out) {
