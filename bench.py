@@ -109,6 +109,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-vs10", action="store_true",
                     help="skip the full count of vertically symmetric order-10 squares")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--profile-only", action="store_true",
                     help="a few persistent launches only (for rocprofv3 runs)")
     return ap.parse_args()
@@ -393,6 +395,21 @@ def main():
                   "exact": int(d_total.item()) == ORDER8_FIXED and int(d_status.item()) == 0}
     del hd, hm, hc
 
+    # ---------------- serving: continuous batching of the request mix on the device ----------------
+    serving = None
+    if not args.no_serve:
+        from paper_1709_02599_amd import serve
+        rows = []
+        with serve.Server() as srv:
+            serve.sweep(jobs=args.serve_jobs, fractions=(0.5,), server=srv, emit=rows.append)
+            alloc = srv.info()["allocated_bytes"]
+        keep = ("jobs", "seconds", "jobs_per_s", "squares_per_s", "max_concurrency", "p50_ms", "p99_ms", "mean_ms")
+        serving = {"workload": f"{args.serve_jobs} requests: order uniform in 7-9, plain or vertically symmetric, "
+                               "first row 0..N-1 plus k in [N, 3N] random consistent cells",
+                   "closed_loop": {k: rows[0][k] for k in keep},
+                   "poisson_half_capacity": {k: rows[1][k] for k in keep},
+                   "server_allocated_bytes": alloc}
+
     # ---------------- CPU oracle on a bounded sample of the same workload ----------------
     # The oracle builds its own sample: seeded canonical hourglasses (its own
     # classes), each extended by every filling of row 1 along its own order.
@@ -483,6 +500,7 @@ def main():
         "alg_ops_per_launch": alg_ops,
         "split_seconds_host": split_s,
         "sustained_full_count": sustained,
+        "serving": serving,
         "exact": (all(r["exact"] for r in results.values()) and all(g["exact"] for g in graph.values())
                   and order7["exact"] and (vs10 is None or vs10["exact"]) and end_to_end["exact"]),
     }

@@ -53,10 +53,11 @@ enum {
     DLS_ENOMEM = -3,   /* host or device allocation failed                    */
     DLS_EDEVICE = -4,  /* HIP runtime error, no device, or kernel fault flag  */
     DLS_EPATTERN = -5, /* a prefix's assigned cells differ from the pattern   */
-    DLS_ECAPTURE = -6  /* the stream is under HIP graph capture and the call
+    DLS_ECAPTURE = -6, /* the stream is under HIP graph capture and the call
                           would allocate (first call on the stream, or a
                           larger batch than any before) or asked for
                           kernel timing                                     */
+    DLS_EBUSY = -7     /* serving: no ring slot or task-pool room free now   */
 };
 
 const char *dls_strerror(int err);
@@ -122,6 +123,17 @@ int dls_split_from(int n, uint32_t flags, const uint8_t *base, int depth,
  * values increasing.  Two-call pattern and errors as dls_split_from. */
 int dls_split_cells(int n, uint32_t flags, const uint8_t *base, const int *cells, int ncells,
                     uint8_t *prefixes_out, int64_t cap, int64_t *num_out);
+
+/* Workunits to a target count (Sec. 5.2), breadth-first: every consistent
+ * assignment of the first d cells of the dls_order() sequence after `base`
+ * (with DLS_VSYM left-half cells, each with its mirror), for the smallest d
+ * with at least min_tasks of them, or d = max_depth (never deeper than two
+ * cells before the end).  The counts of the workunits sum to the count of
+ * base.  Two-call pattern (prefixes_out NULL: only *num_out); DLS_ERANGE if
+ * cap is too small.  P = 0 for an inconsistent base.  Host only; the serving
+ * calls split requests this way. */
+int dls_split_target(int n, uint32_t flags, const uint8_t *base, int64_t min_tasks, int max_depth,
+                     uint8_t *prefixes_out, int64_t cap, int64_t *num_out);
 
 /* Cost of a fill order (Sec. 2.3: the order decides the speed, never the
  * count): over the host prefixes [num][n*n], the number of downward DFS
@@ -345,6 +357,63 @@ int dls_reduce_weighted(const uint64_t *d_counts, const uint32_t *d_mult, int64_
  * and/or/xor/add chains on every lane of `blocks` x 256 threads; d_sink gets
  * one word per thread.  Used to measure the achievable integer-op peak. */
 int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream);
+
+/*
+ * Serving: counting requests that arrive while others run, batched
+ * continuously on the device.  A server holds one long-running kernel on its
+ * own non-blocking stream, serving requests of every order 4..9 with or
+ * without DLS_VSYM, a ring of max_jobs (1..256) job slots and a pool of
+ * pool_bytes of workunit cells, both in host-pinned memory.  A request is
+ * one prefix; the server splits it on the host into at least min_tasks
+ * workunits (Sec. 5.2: the counts of a split sum to the count of the
+ * prefix), writes them to the pool (each workunit padded to a multiple of 16
+ * bytes: 64 bytes at orders 7 and 8, 96 at order 9) and publishes the job in
+ * the ring; no stream operation is involved.  The running kernel takes jobs
+ * oldest first as its waves free up: waves of different jobs, and of
+ * different orders, run side by side, so a request admitted while others
+ * run is served at once.  The kernel keeps each job's outstanding pieces
+ * and computes its total (the exact count of the request, the definition of
+ * Sec. 1) on the device; the piece that finishes a job writes its result to
+ * host-pinned memory, read by dls_server_poll.  The kernel leaves after 50
+ * ms without work and is launched again by the next submit or poll.
+ */
+typedef struct dls_server dls_server;
+
+/* launch (may be NULL): blocks_per_cu (1 or 2 workgroups of 256 per CU;
+ * default 2), refill_every (default 64), chunk_min = workunits a wave takes
+ * from a job at once (default 4), order_variant (fill order); block 0 or
+ * 256; other fields ignored.  A request is split at most 24 cells deep.
+ * DLS_EINVAL for bad arguments, DLS_ENOMEM. */
+int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch, dls_server **out);
+
+/* Admits one request of order n (4..9) and flags (0 or DLS_VSYM): prefix is
+ * a host array of n*n cells.  *ticket_out identifies it for dls_server_poll.
+ * DLS_EBUSY: no ring slot, or no contiguous pool room for its workunits, is
+ * free now (nothing was done; retry once a job has been polled done) --
+ * admission follows the server's real allocation.  DLS_ERANGE: its
+ * workunits need more than the whole pool.  A request whose count is 0
+ * without search (inconsistent prefix; vertical symmetry at odd n) is done
+ * at once.  Thread-safe per server. */
+int dls_server_submit(dls_server *s, int n, uint32_t flags, const uint8_t *prefix, int64_t min_tasks,
+                      int64_t *ticket_out);
+
+/* *done_out = 1 once the request is done; then *count_out (may be NULL) is
+ * its exact count, ticks_out[0..1] (may be NULL) the device times
+ * (s_memrealtime, 100 MHz) when its job was first taken up and when it
+ * finished (0 for requests done without search), and the ticket is retired
+ * (its slot and pool room freed).  DLS_EINVAL for an unknown ticket. */
+int dls_server_poll(dls_server *s, int64_t ticket, uint64_t *count_out, uint64_t *ticks_out, int *done_out);
+
+/* Bytes the server allocated (device and host-pinned), free pool bytes,
+ * free ring slots, launches of the serving kernel so far (any pointer may
+ * be NULL). */
+int dls_server_info(dls_server *s, int64_t *allocated_bytes, int64_t *pool_free, int *slots_free,
+                    int64_t *launches);
+
+/* Stops the kernel (bounded wait) and frees everything.  Requests not polled
+ * done are dropped.  DLS_EDEVICE if the kernel did not stop (the server's
+ * memory is then not freed). */
+int dls_server_destroy(dls_server *s);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,8 @@ __all__ = [
     "dls_count_async_ex", "dls_count_async_noalloc", "dls_count_async_stats", "dls_valu_probe", "DlsLaunch",
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
     "dls_count_cells_async", "dls_split_cells", "dls_order_cost",
-    "dls_hourglass_classes_async", "hourglass_classes_gpu",
+    "dls_hourglass_classes_async", "hourglass_classes_gpu", "DLS_EBUSY", "dls_server_create",
+    "dls_server_submit", "dls_server_poll", "dls_server_info", "dls_server_destroy", "dls_split_target",
 ]
 
 DLS_VSYM = 1 << 0
@@ -30,6 +31,7 @@ DLS_SYMBREAK = 1 << 1
 DLS_PLAIN = 1 << 2
 DLS_EMPTY = 0xFF
 DLS_ECAPTURE = -6
+DLS_EBUSY = -7
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdls.so")
 
@@ -112,6 +114,19 @@ def _load() -> ctypes.CDLL:
                                                  ctypes.c_int, u8p, vp, ctypes.c_int64, vp, vp, vp,
                                                  ctypes.POINTER(DlsLaunch)]),
     }
+    sig.update({
+        "dls_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(DlsLaunch),
+                                             ctypes.POINTER(vp)]),
+        "dls_server_submit": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64)]),
+        "dls_server_poll": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int)]),
+        "dls_server_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]),
+        "dls_server_destroy": (ctypes.c_int, [vp]),
+        "dls_split_target": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int64, ctypes.c_int, u8p,
+                                            ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
@@ -424,3 +439,67 @@ def hourglass_classes_gpu(n: int, stream=None):
     mult = d_mult[:found].cpu().numpy().view(np.uint32).copy()
     order = np.lexsort(out.T[::-1])
     return out[order], mult[order]
+
+
+# --------------------------------------------------------------------------
+# serving (continuous batching on the device): handles are plain ints
+# --------------------------------------------------------------------------
+
+def dls_server_create(max_jobs: int = 128, pool_bytes: int = 64 << 20, launch=None) -> int:
+    """Handle of a new server (one long-running kernel for orders 4..9)."""
+    h = ctypes.c_void_p()
+    lc = _launch(launch)
+    _check(_lib.dls_server_create(max_jobs, pool_bytes, None if lc is None else ctypes.byref(lc),
+                                  ctypes.byref(h)), "dls_server_create")
+    return int(h.value)
+
+
+def dls_server_submit(server: int, n: int, flags: int, prefix, min_tasks: int) -> Optional[int]:
+    """Ticket of the admitted request, or None when the server has no room
+    now (DLS_EBUSY)."""
+    p = _square(n, prefix)
+    t = ctypes.c_int64(0)
+    rc = _lib.dls_server_submit(ctypes.c_void_p(server), n, flags, _u8(p), min_tasks, ctypes.byref(t))
+    if rc == DLS_EBUSY:
+        return None
+    _check(rc, "dls_server_submit")
+    return int(t.value)
+
+
+def dls_server_poll(server: int, ticket: int):
+    """(done, count, (tick_start, tick_end)); count and ticks are None until done."""
+    c = ctypes.c_uint64(0)
+    ticks = (ctypes.c_uint64 * 2)()
+    d = ctypes.c_int(0)
+    _check(_lib.dls_server_poll(ctypes.c_void_p(server), ticket, ctypes.byref(c), ticks, ctypes.byref(d)),
+           "dls_server_poll")
+    if not d.value:
+        return False, None, None
+    return True, int(c.value), (int(ticks[0]), int(ticks[1]))
+
+
+def dls_server_info(server: int) -> dict:
+    b, pf, lc = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    sf = ctypes.c_int(0)
+    _check(_lib.dls_server_info(ctypes.c_void_p(server), ctypes.byref(b), ctypes.byref(pf), ctypes.byref(sf),
+                                ctypes.byref(lc)), "dls_server_info")
+    return {"allocated_bytes": int(b.value), "pool_free": int(pf.value), "slots_free": int(sf.value),
+            "launches": int(lc.value)}
+
+
+def dls_server_destroy(server: int) -> None:
+    _check(_lib.dls_server_destroy(ctypes.c_void_p(server)), "dls_server_destroy")
+
+
+def dls_split_target(n: int, flags: int, base, min_tasks: int, max_depth: int = 24) -> np.ndarray:
+    """Workunits of `base`, split breadth-first to at least min_tasks
+    (or max_depth cells), [P, n*n] uint8."""
+    b = _square(n, base)
+    num = ctypes.c_int64(0)
+    _check(_lib.dls_split_target(n, flags, _u8(b), min_tasks, max_depth, None, 0, ctypes.byref(num)),
+           "dls_split_target")
+    out = np.zeros((num.value, n * n), dtype=np.uint8)
+    if num.value:
+        _check(_lib.dls_split_target(n, flags, _u8(b), min_tasks, max_depth, _u8(out), num.value,
+                                     ctypes.byref(num)), "dls_split_target")
+    return out

@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <thread>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -479,6 +481,59 @@ struct DevBuf {
 };
 
 
+// A partial square with its line masks, for the breadth-first split below.
+struct SplitNode {
+    uint16_t rows[DLS_MAXN], cols[DLS_MAXN], md, ad;
+    uint8_t cell[DLS_MAXN * DLS_MAXN];
+};
+
+// places v at (i, j); false if a row, column or diagonal already holds it
+bool split_place(int n, SplitNode &x, int i, int j, int v) {
+    const uint16_t b = (uint16_t)(1u << v);
+    if ((x.rows[i] & b) || (x.cols[j] & b)) return false;
+    if (i == j && (x.md & b)) return false;
+    if (i + j == n - 1 && (x.ad & b)) return false;
+    x.rows[i] |= b;
+    x.cols[j] |= b;
+    if (i == j) x.md |= b;
+    if (i + j == n - 1) x.ad |= b;
+    x.cell[i * n + j] = (uint8_t)v;
+    return true;
+}
+
+// Workunits of a serving request (Sec. 5.2), breadth-first: the consistent
+// assignments of the first d cells of `order` (with vs: left-half cells, each
+// with its mirror), for the smallest d that gives at least min_tasks of them
+// or d = maxd.  One pass per level, so the cost is that of the levels
+// visited.  Empty if the base is inconsistent or no assignment is.
+std::vector<uint8_t> serve_split(int n, bool vs, const uint8_t *base, const std::vector<int> &order,
+                                 int64_t min_tasks, int maxd) {
+    const int nn = n * n;
+    SplitNode root;
+    std::memset(&root, 0, sizeof(root));
+    std::memset(root.cell, 0xFF, sizeof(root.cell));
+    for (int c = 0; c < nn; ++c)
+        if (base[c] != kEmpty && !split_place(n, root, c / n, c % n, base[c])) return {};
+    std::vector<SplitNode> cur(1, root), next;
+    for (int d = 0; d < maxd && (int64_t)cur.size() < min_tasks && !cur.empty(); ++d) {
+        const int c = order[d], i = c / n, j = c % n, mj = n - 1 - j;
+        next.clear();
+        for (const SplitNode &x : cur) {
+            for (int v = 0; v < n; ++v) {
+                SplitNode y = x;
+                if (!split_place(n, y, i, j, v)) continue;
+                if (vs && mj != j && !split_place(n, y, i, mj, n - 1 - v)) continue;
+                if (vs && mj == j && 2 * v != n - 1) continue;
+                next.push_back(y);
+            }
+        }
+        cur.swap(next);
+    }
+    std::vector<uint8_t> out(cur.size() * (size_t)nn);
+    for (size_t t = 0; t < cur.size(); ++t) std::memcpy(out.data() + t * nn, cur[t].cell, (size_t)nn);
+    return out;
+}
+
 int count_host(int n, uint32_t flags, const uint8_t *prefixes, int64_t num, uint64_t *counts_out, const int *cells,
                int ncells) {
     if (!valid_n(n) || num < 0 || (flags & ~(uint32_t)(DLS_VSYM | DLS_PLAIN))) return DLS_EINVAL;
@@ -555,6 +610,7 @@ const char *dls_strerror(int err) {
         case DLS_ENOMEM: return "out of memory";
         case DLS_EDEVICE: return "HIP device error";
         case DLS_EPATTERN: return "prefix does not match the pattern";
+        case DLS_EBUSY: return "no room now: the server's job ring or task pool is full (retry after a job completes)";
         case DLS_ECAPTURE: return "stream is being captured: device memory would have to be allocated "
                                   "(make one uncaptured call with at least as many prefixes on this "
                                   "stream first) or kernel timing was requested";
@@ -663,6 +719,31 @@ int dls_split_cells(int n, uint32_t flags, const uint8_t *base, const int *cells
         int64_t total = dls::split_write(spec, b.data(), prefixes_out, nullptr, cap);
         *num_out = total;
         if (total > cap) return DLS_ERANGE;
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+    return DLS_OK;
+}
+
+int dls_split_target(int n, uint32_t flags, const uint8_t *base, int64_t min_tasks, int max_depth,
+                     uint8_t *prefixes_out, int64_t cap, int64_t *num_out) {
+    if (!valid_n(n) || !base || !num_out || min_tasks < 1 || max_depth < 0) return DLS_EINVAL;
+    if ((flags & ~(uint32_t)DLS_VSYM) || !valid_cells(n, base)) return DLS_EINVAL;
+    const bool vs = flags & DLS_VSYM;
+    try {
+        std::vector<uint8_t> b(base, base + n * n);
+        std::vector<uint8_t> units;
+        if (!(vs && n % 2 == 1 && n > 1) && (!vs || dls::vs_complete(n, base, b.data()))) {
+            const std::vector<uint8_t> assigned = pattern_of(n, b.data());
+            const std::vector<int> order = dls::fill_order(n, vs, assigned.data(), {});
+            const int maxd = std::min(max_depth, std::max(0, (int)order.size() - 2));
+            units = serve_split(n, vs, b.data(), order, min_tasks, maxd);
+        }
+        const int64_t p = (int64_t)(units.size() / ((size_t)n * n));
+        *num_out = p;
+        if (!prefixes_out) return DLS_OK;
+        if (p > cap) return DLS_ERANGE;
+        std::memcpy(prefixes_out, units.data(), units.size());
     } catch (const std::bad_alloc &) {
         return DLS_ENOMEM;
     }
@@ -920,6 +1001,318 @@ int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream) {
     if (blocks < 1 || iters < 0 || !d_sink) return DLS_EINVAL;
     return dlsk::launch_valu_probe(blocks, iters, d_sink, (hipStream_t)stream) == hipSuccess ? DLS_OK
                                                                                              : DLS_EDEVICE;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving: one long-running kernel for every order and flags, fed through a
+// job ring in host-pinned memory
+// ---------------------------------------------------------------------------
+
+struct dls_server {
+    int dev = 0;
+    int max_jobs = 0;
+    int64_t pool_bytes = 0;
+    int variant = 0;
+    int max_depth = 24;  // deepest host split of a request
+    dlsk::ServeArgs args{};
+    hipStream_t run = nullptr;
+    hipEvent_t ran = nullptr;  // recorded after every launch of the serving kernel
+    bool launched = false;
+    int64_t launches = 0;
+    dlsk::JobDesc *jobs = nullptr;  // host-pinned
+    dlsk::JobState *state = nullptr;
+    dlsk::JobDone *done = nullptr;  // host-pinned
+    uint32_t *stop = nullptr;       // host-pinned
+    uint8_t *pool = nullptr;        // host-pinned workunit cells
+    size_t device_bytes = 0, pinned_bytes = 0;
+    std::mutex mu;
+    uint64_t next_seq = 1;
+    std::map<int64_t, int64_t> free_ranges;  // prefix pool: byte offset -> length
+    int64_t pool_free = 0;
+    std::vector<int> free_slots;
+    struct Job {
+        int slot = -1;
+        int64_t off = 0, len = 0;
+        uint64_t seq = 0;
+        uint64_t pub = 0;   // job number << 32 | workunits, as published
+        bool done = false;
+        uint64_t count = 0, t0 = 0, t1 = 0;
+    };
+    std::map<int64_t, Job> tickets;
+};
+
+namespace {
+
+void server_release(dls_server *s) {
+    if (s->state) (void)hipFree(s->state);
+    if (s->jobs) (void)hipHostFree(s->jobs);
+    if (s->done) (void)hipHostFree(s->done);
+    if (s->stop) (void)hipHostFree(s->stop);
+    if (s->pool) (void)hipHostFree(s->pool);
+    if (s->ran) (void)hipEventDestroy(s->ran);
+    if (s->run) (void)hipStreamDestroy(s->run);
+    delete s;
+}
+
+// (re)launch the serving kernel unless it is running; caller holds s->mu
+int server_ensure_running(dls_server *s) {
+    if (s->launched) {
+        const hipError_t q = hipEventQuery(s->ran);
+        if (q == hipErrorNotReady) return DLS_OK;
+        if (q != hipSuccess) return hip_fail(q, DLS_EDEVICE);
+    }
+    hipError_t e = dlsk::launch_serve(s->args);
+    if (e == hipSuccess) e = hipEventRecord(s->ran, s->run);
+    if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
+    s->launched = true;
+    ++s->launches;
+    return DLS_OK;
+}
+
+// first-fit byte range of the prefix pool, or -1
+int64_t server_take_range(dls_server *s, int64_t len) {
+    for (auto it = s->free_ranges.begin(); it != s->free_ranges.end(); ++it) {
+        if (it->second < len) continue;
+        const int64_t off = it->first, rest = it->second - len;
+        s->free_ranges.erase(it);
+        if (rest) s->free_ranges[off + len] = rest;
+        s->pool_free -= len;
+        return off;
+    }
+    return -1;
+}
+
+void server_give_range(dls_server *s, int64_t off, int64_t len) {
+    if (len <= 0) return;
+    auto it = s->free_ranges.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != s->free_ranges.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        s->free_ranges.erase(nx);
+    }
+    if (it != s->free_ranges.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            s->free_ranges.erase(it);
+        }
+    }
+    s->pool_free += len;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch, dls_server **out) {
+    if (!out) return DLS_EINVAL;
+    *out = nullptr;
+    if (max_jobs < 1 || max_jobs > dlsk::kServeMaxJobs || pool_bytes < 16 || pool_bytes > (int64_t(1) << 36))
+        return DLS_EINVAL;
+    const int variant = launch ? launch->order_variant : 0;
+    const int bpc = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 2;
+    const int refill = (launch && launch->refill_every) ? launch->refill_every : 64;
+    const int chunk = (launch && launch->chunk_min) ? launch->chunk_min : 4;
+    if (variant < 0 || variant >= dls::kOrderVariants || bpc < 1 || bpc > 2 || refill < 2 || chunk < 1 ||
+        chunk > 65536 || (launch && launch->block && launch->block != 256))
+        return DLS_EINVAL;
+    DeviceState *ds = nullptr;
+    int dev = 0;
+    int rc = device_state(&ds, &dev);
+    if (rc) return rc;
+    dls_server *s = new (std::nothrow) dls_server;
+    if (!s) return DLS_ENOMEM;
+    s->dev = dev;
+    s->max_jobs = max_jobs;
+    s->pool_bytes = (pool_bytes + 15) & ~int64_t(15);
+    s->variant = variant;
+    bool ok = hipMalloc((void **)&s->state, sizeof(dlsk::JobState) * max_jobs) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&s->jobs, sizeof(dlsk::JobDesc) * max_jobs, hipHostMallocCoherent) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&s->done, sizeof(dlsk::JobDone) * max_jobs, hipHostMallocCoherent) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&s->stop, sizeof(uint32_t) * 64, hipHostMallocCoherent) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&s->pool, (size_t)s->pool_bytes, hipHostMallocCoherent) == hipSuccess;
+    if (!ok) {
+        server_release(s);
+        return DLS_ENOMEM;
+    }
+    s->device_bytes = sizeof(dlsk::JobState) * max_jobs;
+    s->pinned_bytes = (sizeof(dlsk::JobDesc) + sizeof(dlsk::JobDone)) * max_jobs + 256 + (size_t)s->pool_bytes;
+    std::memset(s->jobs, 0, sizeof(dlsk::JobDesc) * max_jobs);
+    std::memset(s->done, 0, sizeof(dlsk::JobDone) * max_jobs);
+    std::memset(s->stop, 0, sizeof(uint32_t) * 64);
+    // the server's own non-blocking stream (default priority): nothing else
+    // is ever queued on it, and it never waits for the null stream
+    hipError_t e = hipStreamCreateWithFlags(&s->run, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ran, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemsetAsync(s->state, 0, sizeof(dlsk::JobState) * max_jobs, s->run);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->run);
+    if (e != hipSuccess) {
+        const int r = hip_fail(e, DLS_EDEVICE);
+        server_release(s);
+        return r;
+    }
+    s->free_ranges[0] = s->pool_bytes;
+    s->pool_free = s->pool_bytes;
+    for (int k = max_jobs - 1; k >= 0; --k) s->free_slots.push_back(k);
+    dlsk::ServeArgs &a = s->args;
+    a.block = 256;
+    a.grid = ds->cus * bpc;
+    a.jobs = s->jobs;
+    a.state = s->state;
+    a.done = s->done;
+    a.max_jobs = max_jobs;
+    a.pool = s->pool;
+    a.stop = s->stop;
+    a.published = reinterpret_cast<const uint64_t *>(s->stop + 32);  // its own cache line
+    a.idle_ticks = 100000000ull / 20;  // 50 ms at 100 MHz
+    a.refill_every = refill + (refill & 1);
+    a.chunk = chunk;
+    a.stream = s->run;
+    *out = s;
+    return DLS_OK;
+}
+
+int dls_server_submit(dls_server *s, int n, uint32_t flags, const uint8_t *prefix, int64_t min_tasks,
+                      int64_t *ticket_out) {
+    if (!s || !prefix || !ticket_out || min_tasks < 1) return DLS_EINVAL;
+    if (n < dlsk::kServeMinN || n > dlsk::kServeMaxN || (flags & ~(uint32_t)DLS_VSYM)) return DLS_EINVAL;
+    if (!valid_cells(n, prefix)) return DLS_EINVAL;
+    const bool vs = flags & DLS_VSYM;
+    std::lock_guard<std::mutex> lk(s->mu);
+    dls_server::Job job;
+    job.seq = s->next_seq;
+    try {
+        std::vector<uint8_t> b(prefix, prefix + n * n);
+        bool trivial = false;  // the count is 0 without any work
+        if (vs && n % 2 == 1) trivial = true;  // no vertically symmetric square of odd order > 1
+        if (!trivial && vs && !dls::vs_complete(n, prefix, b.data())) trivial = true;
+        std::vector<uint8_t> units;
+        int64_t p = 0;
+        if (!trivial) {
+            // the shallowest split with at least min_tasks workunits, at most
+            // max_depth cells deep, keeping at least two levels for the search
+            const std::vector<uint8_t> assigned = pattern_of(n, b.data());
+            const std::vector<int> order = dls::fill_order(n, vs, assigned.data(), {}, s->variant);
+            const int maxd = std::min(s->max_depth, std::max(0, (int)order.size() - 2));
+            units = serve_split(n, vs, b.data(), order, min_tasks, maxd);
+            p = (int64_t)(units.size() / ((size_t)n * n));
+            if (p == 0) trivial = true;
+        }
+        if (trivial) {
+            job.done = true;
+            s->tickets[(int64_t)job.seq] = job;
+            *ticket_out = (int64_t)job.seq;
+            ++s->next_seq;
+            return DLS_OK;
+        }
+        const int64_t ps = dlsk::pre_stride(n);
+        if (p * ps > s->pool_bytes || p > (int64_t)0xFFFFFFFF) return DLS_ERANGE;
+        if (s->free_slots.empty()) return DLS_EBUSY;
+        const int64_t off = server_take_range(s, p * ps);
+        if (off < 0) return DLS_EBUSY;
+        const size_t nn = (size_t)n * n;
+        dlsk::Plan plan;
+        const int rc = build_plan(n, vs, pattern_of(n, units.data()).data(), plan, s->variant);
+        if (rc) {
+            server_give_range(s, off, p * ps);
+            return rc;
+        }
+        uint8_t *dst = s->pool + off;
+        for (int64_t t = 0; t < p; ++t) {
+            std::memcpy(dst + t * ps, units.data() + t * nn, nn);
+            std::memset(dst + t * ps + nn, 0xFF, (size_t)(ps - (int64_t)nn));
+        }
+        job.slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        job.off = off;
+        job.len = p * ps;
+        dlsk::JobDesc *jd = &s->jobs[job.slot];
+        jd->plan = plan;
+        jd->n = n;
+        jd->vs = vs ? 1 : 0;
+        jd->pre_off = off;
+        // publish: everything above before the pub word (job number and
+        // size), then the counter idle waves watch
+        job.pub = ((uint64_t)(job.seq & 0xFFFFFFFFu) << 32) | (uint64_t)p;
+        __atomic_store_n(&jd->pub, job.pub, __ATOMIC_RELEASE);
+        __atomic_store_n(reinterpret_cast<uint64_t *>(s->stop + 32), job.pub, __ATOMIC_RELEASE);
+        s->tickets[(int64_t)job.seq] = job;
+        *ticket_out = (int64_t)job.seq;
+        ++s->next_seq;
+        return server_ensure_running(s);
+    } catch (const std::bad_alloc &) {
+        return DLS_ENOMEM;
+    }
+}
+
+int dls_server_poll(dls_server *s, int64_t ticket, uint64_t *count_out, uint64_t *ticks_out, int *done_out) {
+    if (!s || !done_out) return DLS_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return DLS_EINVAL;
+    dls_server::Job &j = it->second;
+    if (!j.done) {
+        const dlsk::JobDone *d = &s->done[j.slot];
+        if (__atomic_load_n(&d->pub, __ATOMIC_ACQUIRE) == j.pub) {
+            j.count = __atomic_load_n(&d->total, __ATOMIC_RELAXED);
+            j.t0 = __atomic_load_n(&d->t_start, __ATOMIC_RELAXED);
+            j.t1 = __atomic_load_n(&d->t_end, __ATOMIC_RELAXED);
+            j.done = true;
+            server_give_range(s, j.off, j.len);
+            s->free_slots.push_back(j.slot);
+        } else {
+            // the kernel leaves after a while without work; a job published
+            // just as it left is served by the next launch
+            const int rc = server_ensure_running(s);
+            if (rc) return rc;
+        }
+    }
+    *done_out = j.done ? 1 : 0;
+    if (j.done) {
+        if (count_out) *count_out = j.count;
+        if (ticks_out) {
+            ticks_out[0] = j.t0;
+            ticks_out[1] = j.t1;
+        }
+        s->tickets.erase(it);
+    }
+    return DLS_OK;
+}
+
+int dls_server_info(dls_server *s, int64_t *allocated_bytes, int64_t *pool_free, int *slots_free,
+                    int64_t *launches) {
+    if (!s) return DLS_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (allocated_bytes) *allocated_bytes = (int64_t)(s->device_bytes + s->pinned_bytes);
+    if (pool_free) *pool_free = s->pool_free;
+    if (slots_free) *slots_free = (int)s->free_slots.size();
+    if (launches) *launches = s->launches;
+    return DLS_OK;
+}
+
+int dls_server_destroy(dls_server *s) {
+    if (!s) return DLS_EINVAL;
+    int rc = DLS_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        __atomic_store_n(&s->stop[0], 1u, __ATOMIC_RELEASE);
+        // the kernel sees the flag within its idle backoff; bounded wait
+        if (s->launched) {
+            for (int t = 0;; ++t) {
+                const hipError_t q = hipEventQuery(s->ran);
+                if (q == hipSuccess) break;
+                if (q != hipErrorNotReady || t > 20000) {
+                    rc = DLS_EDEVICE;
+                    break;
+                }
+                std::this_thread::sleep_for(std::chrono::microseconds(500));
+            }
+        }
+    }
+    if (rc == DLS_OK) server_release(s);  // else the kernel may still run: leak rather than free
+    return rc;
 }
 
 }  // extern "C"

@@ -708,35 +708,16 @@ __device__ __forceinline__ void lm_build_desc(const Plan &plan, unsigned char *s
     }
 }
 
-// ---------------------------------------------------------------------------
-// prep: prefix cells -> task record (one lane per prefix)
-// ---------------------------------------------------------------------------
-
+// One prefix (cells in 32-bit words, four per word) -> its task record and
+// the count it already determines (a dead, complete or one-level prefix).
+// patbits: the cells every prefix of the plan assigns; desc0: the first
+// level's 4-byte descriptor.  *mis: the prefix's assigned cells differ from
+// the pattern (its count is then 0).
 template <int N, bool VS>
-__global__ void __launch_bounds__(256) prep_kernel(const Plan plan, const uint8_t *__restrict__ prefixes,
-                                                   int64_t num, Rec<N, VS> *__restrict__ recs,
-                                                   uint64_t *__restrict__ counts, uint32_t *status) {
+__device__ __forceinline__ Rec<N, VS> prefix_record(const uint32_t *words, const uint32_t *patbits, uint32_t desc0,
+                                                    int nlev, uint32_t origin, uint64_t *count, bool *mismatch) {
     using G = Geo<N, VS>;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= num) return;
     constexpr int NN = N * N;
-    constexpr int NW = (NN + 3) / 4;
-    const uint8_t *sq = prefixes + idx * NN;
-    uint32_t words[NW];
-    if constexpr (NN % 4 == 0) {
-        const uint32_t *w = reinterpret_cast<const uint32_t *>(sq);
-#pragma unroll
-        for (int k = 0; k < NW; ++k) words[k] = w[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            uint32_t x = 0;
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (4 * k + t < NN) x |= (uint32_t)sq[4 * k + t] << (8 * t);
-            words[k] = x;
-        }
-    }
     Lane<N, VS> L;
 #pragma unroll
     for (int k = 0; k < G::WR; ++k) L.R[k] = 0;
@@ -749,7 +730,7 @@ __global__ void __launch_bounds__(256) prep_kernel(const Plan plan, const uint8_
     for (int c = 0; c < NN; ++c) {
         const int i = c / N, j = c % N;
         const uint32_t v = (words[c >> 2] >> (8 * (c & 3))) & 0xFFu;
-        const bool inpat = (plan.patbits[c >> 5] >> (c & 31)) & 1u;
+        const bool inpat = (patbits[c >> 5] >> (c & 31)) & 1u;
         const bool filled = v != 0xFFu;
         mis |= ((inpat != filled) || (filled && v >= (uint32_t)N)) ? 1u : 0u;
         if (!inpat || !filled || v >= (uint32_t)N) continue;
@@ -795,31 +776,66 @@ __global__ void __launch_bounds__(256) prep_kernel(const Plan plan, const uint8_
             }
         }
     }
-    if (mis && status) atomicOr(status, 1u);
+    *mismatch = mis != 0u;
     Rec<N, VS> r;
 #pragma unroll
     for (int k = 0; k < G::WR; ++k) r.R[k] = L.R[k];
 #pragma unroll
     for (int k = 0; k < G::WC; ++k) r.C[k] = L.C[k];
     r.diag = L.md | (L.ad << 16);
-    r.origin = (uint32_t)idx;
+    r.origin = origin;
     r.pad = 0;
-    const int nlev = plan.nlev;
-    uint64_t count = 0;
+    uint64_t cnt = 0;
     if (bad || mis) {
         r.cl = kNone << 16;
     } else if (nlev == 0) {
-        count = 1;  // a complete, consistent square
+        cnt = 1;  // a complete, consistent square
         r.cl = kNone << 16;
     } else {
-        const uint32_t c0 = L.cands(plan.desc[0]);
+        const uint32_t c0 = L.cands(desc0);
         if (nlev == 1) {
-            count = (uint64_t)__builtin_popcount(c0);
+            cnt = (uint64_t)__builtin_popcount(c0);
             r.cl = kNone << 16;
         } else {
             r.cl = c0;  // level 0
         }
     }
+    *count = cnt;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// prep: prefix cells -> task record (one lane per prefix)
+// ---------------------------------------------------------------------------
+
+template <int N, bool VS>
+__global__ void __launch_bounds__(256) prep_kernel(const Plan plan, const uint8_t *__restrict__ prefixes,
+                                                   int64_t num, Rec<N, VS> *__restrict__ recs,
+                                                   uint64_t *__restrict__ counts, uint32_t *status) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= num) return;
+    constexpr int NN = N * N;
+    constexpr int NW = (NN + 3) / 4;
+    const uint8_t *sq = prefixes + idx * NN;
+    uint32_t words[NW];
+    if constexpr (NN % 4 == 0) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(sq);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) words[k] = w[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (4 * k + t < NN) x |= (uint32_t)sq[4 * k + t] << (8 * t);
+            words[k] = x;
+        }
+    }
+    uint64_t count = 0;
+    bool mis = false;
+    const Rec<N, VS> r = prefix_record<N, VS>(words, plan.patbits, plan.desc[0], plan.nlev, (uint32_t)idx, &count, &mis);
+    if (mis && status) atomicOr(status, 1u);
     recs[idx] = r;
     counts[idx] = count;
 }
@@ -1788,6 +1804,374 @@ __global__ void __launch_bounds__(256) valu_probe(int iters, uint32_t *sink) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) r ^= a[k];
     sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
+// ---------------------------------------------------------------------------
+// serving kernel: continuous batching of counting jobs on the device
+// ---------------------------------------------------------------------------
+// One long-running grid (one launch serves many jobs of any order 4..9 and
+// flags) built from the persistent lane machinery above.  The host publishes
+// jobs into a ring of slots in host-pinned memory; a job is one request's
+// prefix split into workunits (Sec. 5.2), whose cells sit in a host-pinned
+// prefix pool.  Every wave works on one job at a time: it copies the job's
+// fill order into its own descriptor table in LDS, takes chunks of the job's
+// workunits (a compare-and-swap on the job's head, which carries the job
+// number, so a slot reused for a later job is never taken from by mistake),
+// turns each into a task record in registers as it starts it, refills idle
+// lanes and, once the job has no untaken workunit, shares subtrees inside the
+// wave.  A finished piece adds its count to the job's total and takes one off
+// the job's outstanding counter; the piece that takes it to zero writes the
+// job's result to host-pinned memory.  A wave whose job has nothing left to
+// take moves, when all its lanes are idle, to the oldest published job that
+// has; a wave that finds none for idle_ticks (or sees the stop flag) leaves.
+// Waves of different jobs -- and of different orders -- run side by side, so
+// jobs that arrive while others run are taken as soon as waves free up.
+//
+// LDS per wave: its descriptor table, the first level's 4-byte descriptor and
+// pattern of the job (for building records), its lanes' stacks (one row of
+// 64 slots per level) and a 64-record mailbox for sharing subtrees.
+constexpr uint32_t kSvTable = 16u * 65u;  // >= 16 B x (64 + 1) (even N <= 8), 8 B x (81 + 1) (N = 9)
+constexpr uint32_t kSvInfo = 64u;         // patbits[8], first descriptor, levels
+constexpr uint32_t kSvStacks = 82u * 128u;  // (81 + 1) rows x 64 lanes x 2 bytes
+constexpr uint32_t kSvMbox = 64u * 48u;     // 64 records of order 9
+constexpr uint32_t kSvWave = kSvTable + kSvInfo + kSvStacks + kSvMbox;
+constexpr int kSvBlock = 256;
+static_assert(kSvWave % 16 == 0, "per-wave LDS regions keep 16-byte alignment");
+
+// system-scope loads of the host-pinned ring (no cached copy is ever used)
+__device__ __forceinline__ uint32_t hload32(const void *p) {
+    return __hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t hload64(const void *p) {
+    return __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Works the job of ring slot `slot` whose pub word is `pub` with this wave
+// until the job has no untaken workunit and every lane of the wave is idle.
+// Returns whether the wave took any workunit.
+template <int N, bool VS>
+__device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pub, unsigned char *wsm, int lane) {
+    using S = StackT<N>;
+    using DT = VLaneDesc<N, VS>;
+    using R = Rec<N, VS>;
+    using G = Geo<N, VS>;
+    constexpr uint32_t DB = DT::DB;
+    constexpr int NN = N * N;
+    constexpr int PS = (NN + 15) & ~15;  // pre_stride(N)
+    static_assert(DB * (uint32_t)(NN + 1) <= kSvTable, "descriptor table");
+    static_assert((uint32_t)(NN + 1) * 64u * sizeof(S) <= kSvStacks, "stacks");
+    static_assert(64u * sizeof(R) <= kSvMbox, "mailbox");
+    const uint64_t below = (1ull << lane) - 1ull;
+    const JobDesc *jd = &a.jobs[slot];
+    JobState *js = &a.state[slot];
+    const uint64_t seq32 = pub >> 32;                 // job number
+    const int64_t ntasks = (int64_t)(pub & 0xFFFFFFFFull);  // its workunits
+    const int nlev = (int)hload32(&jd->plan.nlev);
+    if (nlev < 0 || nlev > NN) return false;  // never for a published job; keeps the table in bounds
+    // launch parameters in uniform registers (not re-read from the argument
+    // struct inside the search loop)
+    const int refill_every = __builtin_amdgcn_readfirstlane(a.refill_every);
+    const uint64_t chunk = (uint64_t)__builtin_amdgcn_readfirstlane(a.chunk);
+    JobDone *done_rec = &a.done[slot];
+    const int last = nlev - 1;
+    const uint8_t *pre = a.pool + (int64_t)hload64(&jd->pre_off);
+
+    // the job's plan into this wave's LDS: descriptor table, pattern, first level
+    const uint32_t dbase = lds_of(wsm);
+    uint32_t *info = reinterpret_cast<uint32_t *>(wsm + kSvTable);
+    for (int k = lane; k < nlev; k += 64) {
+        const uint32_t d = hload32(&jd->plan.desc[k]);
+        const uint32_t keep = (N <= 8 && k != nlev - 1) ? G::ALL : 0u;
+        if constexpr (DT::DW) {
+            const uint32_t z = (d >> 16) & 1u ? 0u : ((d >> 17) & 1u ? 8u : kDwNone);
+            reinterpret_cast<uint4 *>(wsm)[k] = make_uint4(d & 63u, (d >> 8) & 63u, z, 0u);
+        } else {
+            reinterpret_cast<uint2 *>(wsm)[k] = make_uint2((d & 0xFFu) | ((d_md(d) & G::ALL) << 16),
+                                                           ((d >> 8) & 0xFFu) | (keep << 8) | ((d_ad(d) & G::ALL) << 16));
+        }
+    }
+    if constexpr (DT::DW) {
+        if (lane == 0) reinterpret_cast<uint4 *>(wsm)[nlev] = make_uint4(0u, 0u, kDwSentinel, 1u);
+    }
+    if (lane < 8) info[lane] = hload32(&jd->plan.patbits[lane]);
+    if (lane == 8) info[8] = nlev > 0 ? hload32(&jd->plan.desc[0]) : 0u;
+    const uint32_t loff = kSvTable + kSvInfo + (uint32_t)lane * (uint32_t)sizeof(S);
+    const uint32_t lane_off = dbase + loff;
+    const uint32_t stride = 64u * (uint32_t)sizeof(S);
+    const uint32_t kst = stride / DB;
+    const uint32_t sc0 = lane_off - dbase * kst;
+    auto slot_of = [&](int l) -> S * { return reinterpret_cast<S *>(wsm + (loff + (uint32_t)l * stride)); };
+    R *mbox = reinterpret_cast<R *>(wsm + kSvTable + kSvInfo + kSvStacks);
+    const uint32_t da_last = dbase + DB * (uint32_t)(last > 0 ? last : 0);
+    lds_st<S>(lane_off, (S)0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t patbits[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) patbits[k] = info[k];
+    const uint32_t desc0 = info[8];
+
+    VLane<N, VS> L;
+#pragma unroll
+    for (int k = 0; k < G::WR; ++k) L.R[k] = 0;
+#pragma unroll
+    for (int k = 0; k < G::WC; ++k) L.C[k] = 0;
+    L.mdh = L.adh = 0u;
+    L.cand = 0u;
+    L.da = L.da0 = dbase;
+    L.sa = lane_off;
+    L.cur = DT::load(dbase);
+    L.cnt = 0;
+    L.c32 = 0u;
+    bool has = false;
+    bool job_left = true;
+    bool took = false;
+    uint64_t cb = 0, ce = 0;
+    auto start = [&](const R &r) {
+        L.from_rec(r, dbase, last, lane_off, stride);
+        lds_st<S>(L.sa, (S)0);
+    };
+
+    for (;;) {
+        if (__ballot(has && !L.done())) {
+            for (int it = 0; it < refill_every; it += 2) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) L.template step<S>(kst, sc0, da_last);
+            }
+        }
+        L.flush();
+        if (has && L.done()) {
+            // The piece's count goes into the job's total, then one piece
+            // less is outstanding.  Both are device-scope atomics performed
+            // where every wave's atomics meet; the decrement's operand depends
+            // on the add's result, so the add is done before the decrement is
+            // issued, and the piece that takes the counter to zero finds
+            // every piece's count in the total (no cache write-back or
+            // invalidation on this path).
+            const uint64_t prev =
+                __hip_atomic_fetch_add(&js->total, L.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // -1, computed from the add's result (a total never reaches 2^64 - 1)
+            const uint64_t dec = prev == ~0ull ? 0ull : ~0ull;
+            const uint64_t left =
+                __hip_atomic_fetch_add(&js->remaining, dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (left == 1) {
+                // the job's last piece: its result to host-pinned memory
+                JobDone *d = done_rec;
+                const uint64_t tot = __hip_atomic_fetch_add(&js->total, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t ts = __hip_atomic_load(&js->t_start, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&d->total, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&d->t_start, ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&d->t_end, (uint64_t)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&d->pub, pub, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            has = false;
+            L.cnt = 0;
+        }
+        uint64_t want = __ballot(!has);
+
+        // ---------------- idle lanes take workunits of the job ----------------
+        if (want && job_left) {
+            const uint64_t k = (uint64_t)__popcll(want);
+            const uint64_t rank = (uint64_t)__popcll(want & below);
+            const int leader = __ffsll((unsigned long long)want) - 1;
+            int64_t my_id = -1;
+            uint64_t given = 0;
+            while (given < k) {
+                if (cb >= ce) {
+                    uint64_t got = 0, b0 = 0;
+                    if (lane == leader) {
+                        uint64_t h = __hip_atomic_load(&js->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        for (int tries = 0; tries < 64; ++tries) {
+                            const uint64_t taken = h & 0xFFFFFFFFull;
+                            if ((h >> 32) != seq32 || taken >= (uint64_t)ntasks) break;
+                            const uint64_t rem = (uint64_t)ntasks - taken;
+                            const uint64_t sz = rem < chunk ? rem : chunk;
+                            if (__hip_atomic_compare_exchange_strong(&js->head, &h, h + sz, __ATOMIC_RELAXED,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                                got = sz;
+                                b0 = taken;
+                                break;
+                            }
+                        }
+                    }
+                    got = bcast64(got, leader);
+                    b0 = bcast64(b0, leader);
+                    if (!got) {
+                        job_left = false;
+                        break;
+                    }
+                    cb = b0;
+                    ce = b0 + got;
+                    took = true;
+                }
+                const uint64_t take = (k - given) < (ce - cb) ? (k - given) : (ce - cb);
+                if (!has && rank >= given && rank < given + take) my_id = (int64_t)(cb + (rank - given));
+                cb += take;
+                given += take;
+            }
+            if (my_id >= 0) {
+                // the workunit's cells from the pool (16-byte loads), then its record
+                uint32_t words[PS / 4];
+                const uint32_t *src = reinterpret_cast<const uint32_t *>(pre + (size_t)my_id * PS);
+#pragma unroll
+                for (int q = 0; q < PS / 4; ++q) words[q] = hload32(src + q);
+                uint64_t c0 = 0;
+                bool mis = false;
+                const R r = prefix_record<N, VS>(words, patbits, desc0, nlev, 0u, &c0, &mis);
+                start(r);
+                L.cnt = c0;  // dead, complete or one-level workunits: counted here
+                has = true;
+            }
+            want = __ballot(!has);
+        }
+
+        // ---------------- nothing left to take: share subtrees inside the wave ----------------
+        if (want && want != ~0ull && !job_left) {
+            int lvl = -1;
+            if (has && !L.done()) {
+                const int dep = L.depth(dbase);
+                const int top = dep < last - 1 ? dep : last - 1;
+                for (int l = L.start_level(dbase); l < top; ++l) {
+                    const uint32_t sv = *slot_of(l);
+                    if (sv & (sv - 1u)) {
+                        lvl = l;
+                        break;
+                    }
+                }
+            }
+            const uint64_t donors = __ballot(lvl >= 0);
+            const uint64_t nd = (uint64_t)__popcll(donors), ni = (uint64_t)__popcll(want);
+            const uint64_t m = nd < ni ? nd : ni;
+            if (m) {
+                // the new pieces are outstanding before any of them can finish
+                if (lane == 0) __hip_atomic_fetch_add(&js->remaining, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t drank = (uint64_t)__popcll(donors & below);
+                const uint64_t rrank = (uint64_t)__popcll(want & below);
+                const bool take = !has && rrank < m;
+                if (lvl >= 0 && drank < m) mbox[drank] = L.donate(lvl, dbase, slot_of, 0u);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                R got{};
+                if (take) got = mbox[rrank];
+                __builtin_amdgcn_wave_barrier();
+                if (take) {
+                    start(got);
+                    has = true;
+                }
+                want = __ballot(!has);
+            }
+        }
+        if (want == ~0ull && !job_left) return took;
+    }
+}
+
+// The oldest published job that has untaken workunits: its slot, or -1;
+// *pub_out gets its pub word.  Jobs already set up are found in the
+// device-side work states; the host-pinned ring is read only when the host's
+// publish counter has moved since this wave last looked (*seen), and a job
+// found there is set up by the first wave that claims it.  Whether a job is
+// takeable is judged from the claim word alone (job number and size in one
+// word), the same word serve_job works from.
+__device__ __forceinline__ int serve_pick(const ServeArgs &a, int lane, uint64_t now, uint64_t *seen,
+                                          uint64_t *pub_out) {
+    const uint64_t pubc = hload64(a.published);
+    const bool fresh = pubc != *seen;
+    *seen = pubc;
+    uint64_t best = ~0ull, best_claim = 0;
+    for (int j = lane; j < a.max_jobs; j += 64) {
+        JobState *js = &a.state[j];
+        uint64_t c = __hip_atomic_load(&js->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (fresh) {
+            const uint64_t q = hload64(&a.jobs[j].pub);
+            if (q > c) {
+                // a job not set up yet: the first wave to claim it does
+                if (!__hip_atomic_compare_exchange_strong(&js->claim, &c, q, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT))
+                    continue;  // being set up by another wave: seen next time
+                __hip_atomic_store(&js->total, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&js->t_start, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&js->remaining, q & 0xFFFFFFFFull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&js->head, q & ~0xFFFFFFFFull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                c = q;
+            }
+        }
+        if (!c) continue;
+        const uint64_t h = __hip_atomic_load(&js->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((h >> 32) == (c >> 32) && (h & 0xFFFFFFFFull) < (c & 0xFFFFFFFFull)) {
+            const uint64_t key = ((c >> 32) << 8) | (uint64_t)j;  // oldest first
+            if (key < best) {
+                best = key;
+                best_claim = c;
+            }
+        }
+    }
+    uint64_t mine = best;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t y = ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(best >> 32), o) << 32) |
+                           (uint32_t)__shfl_xor((int)(uint32_t)best, o);
+        best = y < best ? y : best;
+    }
+    if (best == ~0ull) return -1;
+    const int owner = __ffsll((unsigned long long)__ballot(mine == best)) - 1;
+    *pub_out = bcast64(best_claim, owner);
+    return (int)(best & 0xFFu);
+}
+
+__global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) serve_kernel(ServeArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    unsigned char *wsm = smem + (threadIdx.x >> 6) * kSvWave;  // this wave's LDS
+    uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
+    uint32_t backoff = 1;
+    uint64_t seen = ~0ull;  // publish counter at this wave's last look at the ring
+    uint32_t empty = 0;     // picks in a row that gave the wave no workunit
+    for (;;) {
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        uint64_t pub = 0;
+        const int slot = serve_pick(a, lane, now, &seen, &pub);
+        if (slot >= 0 && empty < 16) {
+            // the descriptor and cells of the job (written by the host before
+            // its pub word) are used only while the slot still holds it
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            bool took = false;
+            if (hload64(&a.jobs[slot].pub) == pub) {
+                const int n = (int)hload32(&a.jobs[slot].n);
+                const bool vs = hload32(&a.jobs[slot].vs) != 0u;
+                switch (n * 2 + (vs ? 1 : 0)) {
+#define DLS_SV_CASE(K)                                                               \
+    case 2 * K: took = serve_job<K, false>(a, slot, pub, wsm, lane); break;         \
+    case 2 * K + 1: took = serve_job<K, true>(a, slot, pub, wsm, lane); break;
+                    DLS_SV_CASE(4) DLS_SV_CASE(5) DLS_SV_CASE(6) DLS_SV_CASE(7) DLS_SV_CASE(8) DLS_SV_CASE(9)
+#undef DLS_SV_CASE
+                    default: break;  // the host publishes only these orders
+                }
+            }
+            if (took) {
+                empty = 0;
+                idle_since = __builtin_amdgcn_s_memrealtime();
+                backoff = 1;
+                continue;
+            }
+            ++empty;
+        } else {
+            empty = 0;
+        }
+        // nothing taken: the stop flag and the idle limit end the wave
+        const bool stop = hload32(a.stop) != 0u;
+        if (stop || now - idle_since > a.idle_ticks) break;
+        // an idle wave looks again after 1, 2, 4, ... up to about 100 us
+        for (uint32_t t = 0; t < backoff; ++t) __builtin_amdgcn_s_sleep(32);
+        backoff = backoff < 128 ? backoff * 2 : 128;
+    }
+}
+
+hipError_t launch_serve(const ServeArgs &a) {
+    if (a.block != kSvBlock) return hipErrorInvalidValue;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(serve_kernel, dim3(a.grid), dim3(a.block), (size_t)(kSvBlock / 64) * kSvWave, a.stream, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -104,6 +104,63 @@ struct LaunchArgs {
     int epasses;           // expansion passes (each one level deeper)
 };
 
+// ---------------------------------------------------------------------------
+// serving: one long-running kernel for every order and flags, fed through a
+// ring of jobs in host-pinned memory
+// ---------------------------------------------------------------------------
+
+// A published job (host-pinned, one per ring slot).  The host writes every
+// field, then pub with release; the kernel reads every field with
+// system-scope atomic loads, pub first.
+struct JobDesc {
+    Plan plan;         // the job's fill order
+    int32_t n;         // order
+    int32_t vs;        // vertical symmetry
+    int64_t pre_off;   // byte offset of the job's first workunit in the prefix pool
+    uint64_t pub;      // job number << 32 | workunits (each pre_stride(n) bytes); 0 = slot never used
+};
+
+// Work state of a job (device memory, one per ring slot, 128 bytes).
+struct JobState {
+    uint64_t head;       // job number << 32 | workunits taken
+    uint64_t remaining;  // pieces not finished: workunits, plus subtrees handed on
+    uint64_t total;      // squares counted so far
+    uint64_t t_start;    // s_memrealtime when the job was first claimed
+    uint64_t claim;      // pub word of the job this state was set up for
+    uint64_t pad[11];
+};
+
+// Result of a job (host-pinned, one per ring slot); pub is written last.
+struct JobDone {
+    uint64_t pub;
+    uint64_t total;
+    uint64_t t_start;  // s_memrealtime ticks (100 MHz)
+    uint64_t t_end;
+};
+
+struct ServeArgs {
+    int block;
+    int grid;
+    const JobDesc *jobs;    // host-pinned
+    JobState *state;
+    JobDone *done;          // host-pinned
+    int max_jobs;
+    const uint8_t *pool;    // host-pinned prefixes
+    const uint32_t *stop;   // host-pinned: nonzero = leave when idle
+    const uint64_t *published;  // host-pinned: seq of the last job published
+    uint64_t idle_ticks;    // a wave with no job for this long leaves
+    int refill_every;
+    int chunk;              // tasks a wave takes from a job at once
+    hipStream_t stream;
+};
+
+constexpr int kServeMinN = 4;
+constexpr int kServeMaxN = 9;
+constexpr int kServeMaxJobs = 256;
+// bytes of one workunit in the prefix pool (n*n cells, padded for 16-byte loads)
+inline int pre_stride(int n) { return (n * n + 15) & ~15; }
+hipError_t launch_serve(const ServeArgs &a);
+
 uint32_t make_desc(int n, bool vs, int i, int j);
 hipError_t launch(const LaunchArgs &a);
 hipError_t launch_valu_probe(int blocks, int iters, uint32_t *sink, hipStream_t stream);

@@ -1,6 +1,12 @@
-"""Serving: requests of different orders, flags and prefix sizes run
-concurrently on the GPU; each count must be the same alone and in the mix,
-and equal to the oracle's (exact integers: tolerance 0)."""
+"""Serving: requests of different orders, flags and prefix sizes batched
+continuously on the GPU by the library's serving kernel (one long-running
+kernel for every order and flags, fed through a job ring it polls).  Each
+count must be the same alone and in the mix and equal the oracle's (exact
+integers: tolerance 0); requests must run on the device at the same time;
+admission must follow the servers' real allocation."""
+import collections
+import time
+
 import numpy as np
 import pytest
 
@@ -20,38 +26,158 @@ def _cuda():
         pytest.skip("no GPU")
 
 
-def _requests(count, seed, k_range=None):
+def _requests(count, seed, k_range=None, rate=1000.0):
     from paper_1709_02599_amd.serve import Request
-    jobs = dls_workloads.job_stream(count, rate=1000.0, seed=seed, k_range=k_range)
+    jobs = dls_workloads.job_stream(count, rate=rate, seed=seed, k_range=k_range)
     return [Request(j.jid, j.n, j.vs, j.prefix, j.arrival) for j in jobs]
 
 
-@pytest.mark.parametrize("host_split", [False, True])
-def test_mix_equals_solo_equals_oracle(host_split):
+def _oracle(reqs):
+    """The oracle's count of every request (grouped by order and flags)."""
+    groups = collections.defaultdict(list)
+    for q in reqs:
+        groups[(q.n, q.vs)].append(q)
+    out = {}
+    for (n, vs), qs in groups.items():
+        c = oracle.count_many(n, np.stack([q.prefix for q in qs]), vs=vs)
+        for q, v in zip(qs, c):
+            out[q.rid] = int(v)
+    return out
+
+
+def test_every_count_equals_the_oracle_in_the_mix():
+    # requests whose counts the oracle finishes in seconds (k in [12, 20])
     from paper_1709_02599_amd.serve import Server
-    reqs = _requests(40, seed=5)
-    srv = Server(slots=4, min_tasks=2048, host_split=host_split)
-    mix = srv.run(reqs, realtime=False)
-    assert [r.rid for r in mix] == [q.rid for q in reqs]
-    for q, r in zip(reqs, mix):
-        flags = dls.DLS_VSYM if q.vs else 0
-        solo = int(dls.dls_count(q.n, flags, q.prefix[None])[0])
-        assert r.count == solo, (q.rid, q.n, q.vs)
-        if solo <= 3_000_000:
-            assert solo == oracle.count(q.n, q.prefix, vs=q.vs), (q.rid, q.n, q.vs)
+    reqs = _requests(64, seed=5, k_range=(12, 20))
+    want = _oracle(reqs)
+    with Server(min_tasks=512) as srv:
+        res = srv.run(reqs, realtime=False)
+    assert [r.rid for r in res] == [q.rid for q in reqs]
+    for q, r in zip(reqs, res):
+        assert r.count == want[q.rid], (q.rid, q.n, q.vs)
         if q.vs and q.n % 2:
-            assert solo == 0
+            assert r.count == 0
+    assert any(want.values())
 
 
-def test_realtime_arrivals_and_admission_by_memory():
+def test_mix_equals_solo_and_jobs_overlap_on_the_device():
+    # the workload's own prefix sizes (k in [N, 3N]): every count equals the
+    # count of the same request served alone; several requests are counted
+    # on the device at the same time (device timestamps of first chunk and
+    # last piece)
+    from paper_1709_02599_amd.serve import Server
+    reqs = _requests(40, seed=7)
+    with Server(min_tasks=2048) as srv:
+        mix = srv.run(reqs, realtime=False)
+        solo = [srv.run([q], realtime=False)[0] for q in reqs]
+        info = srv.info()
+    for q, a, b in zip(reqs, mix, solo):
+        assert a.count == b.count, (q.rid, q.n, q.vs)
+        # the plain count API agrees too
+        assert a.count == int(dls.dls_count(q.n, dls.DLS_VSYM if q.vs else 0, q.prefix[None])[0])
+    small = [q for q, a in zip(reqs, mix) if a.count <= 100_000]
+    want = _oracle(small)
+    for q in small:
+        assert [r for r in mix if r.rid == q.rid][0].count == want[q.rid]
+    # requests were served by a running kernel, not one launch each
+    assert info["launches"] < len(reqs)
+
+
+def test_requests_run_on_the_device_at_the_same_time():
+    # heavier requests (order 8, 6-8 cells beyond the first row) admitted
+    # together: their device intervals (job taken up -> last piece done)
+    # overlap, and each count equals the request's count alone
+    from paper_1709_02599_amd.serve import Request, Server, max_concurrency, overlapping_pairs
+    jobs = dls_workloads.job_stream(12, rate=1000.0, seed=11, orders=(8,), vs_choices=(False,), k_range=(6, 8))
+    reqs = [Request(j.jid, j.n, j.vs, j.prefix, 0.0) for j in jobs]
+    with Server(min_tasks=2048) as srv:
+        mix = srv.run(reqs, realtime=False)
+        assert srv.peak_in_flight >= 2
+    solo = dls.dls_count(8, 0, np.stack([q.prefix for q in reqs]))
+    assert [r.count for r in mix] == [int(c) for c in solo]
+    busy = [r for r in mix if r.dev_end > 0]
+    assert len(busy) >= 2
+    assert max_concurrency(mix) >= 2, [(r.dev_start, r.dev_end) for r in busy]
+    assert overlapping_pairs(mix) >= 1
+
+
+def test_admission_follows_the_pool():
+    # a pool of 256 KiB (4 096 workunits of order 8) and 4 ring slots: at
+    # most a few requests fit at once, the rest wait for room (DLS_EBUSY); the
+    # peak of pool bytes in use never exceeds the pool; every count is exact
+    from paper_1709_02599_amd.serve import Server
+    reqs = _requests(48, seed=5, k_range=(12, 20))
+    want = _oracle(reqs)
+    with Server(pool_bytes=256 << 10, max_jobs=4, min_tasks=256) as srv:
+        res = srv.run(reqs, realtime=False)
+        assert srv.busy_answers > 0
+        assert 0 < srv.peak_pool_used <= 256 << 10
+        info = srv.info()
+        assert info["pool_free"] == 256 << 10 and info["slots_free"] == 4     # all retired
+        assert info["allocated_bytes"] >= 256 << 10
+    for q, r in zip(reqs, res):
+        assert r.count == want[q.rid]
+
+
+def test_realtime_arrivals_and_latency_stats():
     from paper_1709_02599_amd.serve import Server, latency_stats
-    reqs = _requests(16, seed=7)
-    # host-split requests of about 1024 workunits: a 1 MiB budget admits one
-    # at a time mostly
-    srv = Server(slots=2, mem_budget=1 << 20, min_tasks=1024, host_split=True)
-    res = srv.run(reqs, realtime=True)
-    ref = Server(slots=4).run(reqs, realtime=False)
-    assert [a.count for a in res] == [b.count for b in ref]
+    reqs = _requests(24, seed=9, k_range=(12, 20), rate=400.0)
+    want = _oracle(reqs)
+    with Server(min_tasks=512) as srv:
+        res = srv.run(reqs, realtime=True)
+    assert [r.count for r in res] == [want[q.rid] for q in reqs]
     st = latency_stats(res)
-    assert st["n"] == 16 and st["p99_ms"] >= st["p50_ms"] > 0
-    assert sum(v["n"] for v in st["per_order"].values()) == 16
+    assert st["n"] == 24 and st["p99_ms"] >= st["p50_ms"] > 0
+    assert sum(v["n"] for v in st["per_order"].values()) == 24
+    assert all(r.done >= r.admitted >= r.arrival for r in res)
+
+
+def test_server_leaves_when_idle_and_comes_back():
+    # the kernel leaves after 50 ms without work; the next request launches it again
+    n = 7
+    h = dls.dls_server_create(max_jobs=8, pool_bytes=1 << 20)
+    try:
+        p = oracle.identity_prefix(n)
+        counts = []
+        for rep in range(2):
+            t = dls.dls_server_submit(h, n, 0, p, 256)
+            assert t is not None
+            t_end = time.time() + 30
+            while True:
+                done, c, ticks = dls.dls_server_poll(h, t)
+                if done:
+                    break
+                assert time.time() < t_end, "request not done"
+                time.sleep(0.0005)
+            counts.append(c)
+            assert ticks[1] >= ticks[0] > 0
+            time.sleep(0.2)                          # longer than the idle limit
+        assert counts == [171200, 171200]            # order 7, first row fixed
+        assert dls.dls_server_info(h)["launches"] >= 2
+        # an inconsistent prefix is done at once with count 0
+        bad = p.copy()
+        bad[n] = 0                                   # (1,0) repeats the value of (0,0)
+        t = dls.dls_server_submit(h, n, 0, bad, 256)
+        assert dls.dls_server_poll(h, t)[:2] == (True, 0)
+        with pytest.raises(dls.DLSError):
+            dls.dls_server_poll(h, t)                # retired
+        # vertical symmetry at an odd order: 0 at once
+        t = dls.dls_server_submit(h, n, dls.DLS_VSYM, p, 256)
+        assert dls.dls_server_poll(h, t)[:2] == (True, 0)
+    finally:
+        dls.dls_server_destroy(h)
+
+
+def test_server_argument_errors():
+    h = dls.dls_server_create(max_jobs=2, pool_bytes=4096)
+    try:
+        with pytest.raises(dls.DLSError):
+            dls.dls_server_submit(h, 10, 0, oracle.identity_prefix(10), 16)   # beyond the served orders
+        with pytest.raises(dls.DLSError):
+            dls.dls_server_submit(h, 8, dls.DLS_SYMBREAK, oracle.identity_prefix(8), 16)
+        # a split larger than the whole pool (4 KiB = 64 workunits of order 8)
+        with pytest.raises(dls.DLSError) as ei:
+            dls.dls_server_submit(h, 8, 0, oracle.identity_prefix(8), 100_000)
+        assert ei.value.code == -2
+    finally:
+        dls.dls_server_destroy(h)
