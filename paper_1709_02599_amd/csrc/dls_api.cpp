@@ -481,23 +481,25 @@ struct DevBuf {
 };
 
 
-// A partial square with its line masks, for the breadth-first split below.
+// A node of the breadth-first split below: the line masks of the base plus
+// the values placed so far, and those values (the cells are the first levels
+// of the order, so the square is rebuilt from the base at the end).
 struct SplitNode {
     uint16_t rows[DLS_MAXN], cols[DLS_MAXN], md, ad;
-    uint8_t cell[DLS_MAXN * DLS_MAXN];
+    uint8_t val[64];  // value placed at level t
 };
+constexpr int kSplitMaxDepth = 64;
 
 // places v at (i, j); false if a row, column or diagonal already holds it
-bool split_place(int n, SplitNode &x, int i, int j, int v) {
+bool split_place(int n, uint16_t *rows, uint16_t *cols, uint16_t &md, uint16_t &ad, int i, int j, int v) {
     const uint16_t b = (uint16_t)(1u << v);
-    if ((x.rows[i] & b) || (x.cols[j] & b)) return false;
-    if (i == j && (x.md & b)) return false;
-    if (i + j == n - 1 && (x.ad & b)) return false;
-    x.rows[i] |= b;
-    x.cols[j] |= b;
-    if (i == j) x.md |= b;
-    if (i + j == n - 1) x.ad |= b;
-    x.cell[i * n + j] = (uint8_t)v;
+    if ((rows[i] & b) || (cols[j] & b)) return false;
+    if (i == j && (md & b)) return false;
+    if (i + j == n - 1 && (ad & b)) return false;
+    rows[i] |= b;
+    cols[j] |= b;
+    if (i == j) md |= b;
+    if (i + j == n - 1) ad |= b;
     return true;
 }
 
@@ -509,28 +511,46 @@ bool split_place(int n, SplitNode &x, int i, int j, int v) {
 std::vector<uint8_t> serve_split(int n, bool vs, const uint8_t *base, const std::vector<int> &order,
                                  int64_t min_tasks, int maxd) {
     const int nn = n * n;
+    maxd = std::min(maxd, kSplitMaxDepth);
     SplitNode root;
     std::memset(&root, 0, sizeof(root));
-    std::memset(root.cell, 0xFF, sizeof(root.cell));
     for (int c = 0; c < nn; ++c)
-        if (base[c] != kEmpty && !split_place(n, root, c / n, c % n, base[c])) return {};
+        if (base[c] != kEmpty && !split_place(n, root.rows, root.cols, root.md, root.ad, c / n, c % n, base[c]))
+            return {};
     std::vector<SplitNode> cur(1, root), next;
-    for (int d = 0; d < maxd && (int64_t)cur.size() < min_tasks && !cur.empty(); ++d) {
+    int d = 0;
+    for (; d < maxd && (int64_t)cur.size() < min_tasks && !cur.empty(); ++d) {
         const int c = order[d], i = c / n, j = c % n, mj = n - 1 - j;
         next.clear();
+        next.reserve(cur.size() * 2);
+        const uint16_t all = (uint16_t)((1u << n) - 1u);
         for (const SplitNode &x : cur) {
-            for (int v = 0; v < n; ++v) {
+            // values free at (i, j) before trying them one by one
+            uint16_t used = x.rows[i] | x.cols[j];
+            if (i == j) used |= x.md;
+            if (i + j == n - 1) used |= x.ad;
+            for (uint16_t fr = (uint16_t)(all & ~used); fr; fr &= (uint16_t)(fr - 1)) {
+                const int v = __builtin_ctz(fr);
                 SplitNode y = x;
-                if (!split_place(n, y, i, j, v)) continue;
-                if (vs && mj != j && !split_place(n, y, i, mj, n - 1 - v)) continue;
+                if (!split_place(n, y.rows, y.cols, y.md, y.ad, i, j, v)) continue;
+                if (vs && mj != j && !split_place(n, y.rows, y.cols, y.md, y.ad, i, mj, n - 1 - v)) continue;
                 if (vs && mj == j && 2 * v != n - 1) continue;
+                y.val[d] = (uint8_t)v;
                 next.push_back(y);
             }
         }
         cur.swap(next);
     }
     std::vector<uint8_t> out(cur.size() * (size_t)nn);
-    for (size_t t = 0; t < cur.size(); ++t) std::memcpy(out.data() + t * nn, cur[t].cell, (size_t)nn);
+    for (size_t t = 0; t < cur.size(); ++t) {
+        uint8_t *q = out.data() + t * nn;
+        std::memcpy(q, base, (size_t)nn);
+        for (int l = 0; l < d; ++l) {
+            const int c = order[l], i = c / n, j = c % n;
+            q[c] = cur[t].val[l];
+            if (vs && n - 1 - j != j) q[i * n + (n - 1 - j)] = (uint8_t)(n - 1 - cur[t].val[l]);
+        }
+    }
     return out;
 }
 

@@ -359,3 +359,49 @@ def test_order_cost_rejects_assigned_cells():
     base = oracle.identity_prefix(6)
     with pytest.raises(dls.DLSError):
         dls.dls_order_cost(6, 0, [0, 7], base[None])
+
+
+# --------------------------------------------------------------------------
+# breadth-first split to a target size (the serving split, Sec. 5.2)
+# --------------------------------------------------------------------------
+
+def _oracle_cells(n, vs, order, d):
+    cells = []
+    for c in order[:d]:
+        cells.append(c)
+        m = (c // n) * n + (n - 1 - c % n)
+        if vs and m != c:
+            cells.append(m)
+    return cells
+
+
+@pytest.mark.parametrize("n,vs", [(5, False), (6, False), (7, False), (8, False), (6, True), (8, True)])
+def test_split_target_equals_the_oracle_workunits(n, vs):
+    rng = workloads.SplitMix64(300 + n + vs)
+    for trial in range(6):
+        base = workloads.random_prefix(n, rng.below(n + 1), vs, rng)
+        target = 1 + rng.below(400)
+        got = dls.dls_split_target(n, int(vs), base, target, 24)
+        order = oracle.fill_order(n, np.flatnonzero(base != 0xFF).tolist(), vs=vs)
+        maxd = min(24, max(0, len(order) - 2))
+        # the smallest depth that reaches the target (or the deepest allowed)
+        for d in range(maxd + 1):
+            want = oracle.assignments(n, base, _oracle_cells(n, vs, order, d), vs=vs)
+            if len(want) >= target or d == maxd or len(want) == 0:
+                break
+        if len(want) == 0:
+            assert len(got) == 0
+            continue
+        a = {bytes(r) for r in got}
+        b = {bytes(r) for r in want}
+        assert len(a) == len(got) and a == b, (n, vs, trial, d, len(got), len(want))
+
+
+def test_split_target_counts_sum_to_the_base():
+    # Sec. 5.2: the workunits' counts add up to the count of the prefix
+    n = 6
+    rng = workloads.SplitMix64(17)
+    for vs in (False, True):
+        base = workloads.random_prefix(n, 3, vs, rng)
+        units = dls.dls_split_target(n, int(vs), base, 50, 24)
+        assert int(oracle.count_many(n, units, vs=vs).sum()) == oracle.count(n, base, vs=vs)
