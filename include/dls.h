@@ -374,8 +374,10 @@ int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream);
  * run is served at once.  The kernel keeps each job's outstanding pieces
  * and computes its total (the exact count of the request, the definition of
  * Sec. 1) on the device; the piece that finishes a job writes its result to
- * host-pinned memory, read by dls_server_poll.  The kernel leaves after 50
- * ms without work and is launched again by the next submit or poll.
+ * host-pinned memory, read by dls_server_poll.  The grid leaves as a whole:
+ * once a wave has found no job for 50 ms while no wave is inside a job, every
+ * wave leaves, and the next submit or poll launches the kernel again; while
+ * any job runs, every wave of the grid stays (none leaves on its own).
  */
 typedef struct dls_server dls_server;
 
@@ -409,6 +411,13 @@ int dls_server_poll(dls_server *s, int64_t ticket, uint64_t *count_out, uint64_t
  * be NULL). */
 int dls_server_info(dls_server *s, int64_t *allocated_bytes, int64_t *pool_free, int *slots_free,
                     int64_t *launches);
+
+/* Waves of the serving kernel running now (*live_out) and waves of its grid
+ * (*grid_out: 4 per workgroup, blocks_per_cu workgroups per CU); read from
+ * host-pinned flags each wave sets while it runs (either pointer may be
+ * NULL).  While the kernel runs, *live_out equals *grid_out except while the
+ * grid starts or leaves.  DLS_EINVAL for a NULL server. */
+int dls_server_waves(dls_server *s, int *live_out, int *grid_out);
 
 /* Stops the kernel (bounded wait) and frees everything.  Requests not polled
  * done are dropped.  DLS_EDEVICE if the kernel did not stop (the server's

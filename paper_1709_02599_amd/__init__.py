@@ -23,7 +23,8 @@ __all__ = [
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
     "dls_count_cells_async", "dls_split_cells", "dls_order_cost",
     "dls_hourglass_classes_async", "hourglass_classes_gpu", "DLS_EBUSY", "dls_server_create",
-    "dls_server_submit", "dls_server_poll", "dls_server_info", "dls_server_destroy", "dls_split_target",
+    "dls_server_submit", "dls_server_poll", "dls_server_info", "dls_server_waves", "dls_server_destroy",
+    "dls_split_target",
 ]
 
 DLS_VSYM = 1 << 0
@@ -123,6 +124,7 @@ def _load() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int)]),
         "dls_server_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]),
+        "dls_server_waves": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "dls_server_destroy": (ctypes.c_int, [vp]),
         "dls_split_target": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int64, ctypes.c_int, u8p,
                                             ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
@@ -485,6 +487,14 @@ def dls_server_info(server: int) -> dict:
                                 ctypes.byref(lc)), "dls_server_info")
     return {"allocated_bytes": int(b.value), "pool_free": int(pf.value), "slots_free": int(sf.value),
             "launches": int(lc.value)}
+
+
+def dls_server_waves(server: int) -> tuple:
+    """(waves of the serving kernel running now, waves of its grid)."""
+    live, grid = ctypes.c_int(0), ctypes.c_int(0)
+    _check(_lib.dls_server_waves(ctypes.c_void_p(server), ctypes.byref(live), ctypes.byref(grid)),
+           "dls_server_waves")
+    return int(live.value), int(grid.value)
 
 
 def dls_server_destroy(server: int) -> None:

@@ -1042,9 +1042,12 @@ struct dls_server {
     bool launched = false;
     int64_t launches = 0;
     dlsk::JobDesc *jobs = nullptr;  // host-pinned
-    dlsk::JobState *state = nullptr;
+    dlsk::JobState *state = nullptr;  // followed by the gate word (device)
+    uint64_t *gate = nullptr;
     dlsk::JobDone *done = nullptr;  // host-pinned
     uint32_t *stop = nullptr;       // host-pinned
+    uint32_t *alive = nullptr;      // host-pinned: one word per wave of the grid
+    int waves = 0;
     uint8_t *pool = nullptr;        // host-pinned workunit cells
     size_t device_bytes = 0, pinned_bytes = 0;
     std::mutex mu;
@@ -1070,6 +1073,7 @@ void server_release(dls_server *s) {
     if (s->jobs) (void)hipHostFree(s->jobs);
     if (s->done) (void)hipHostFree(s->done);
     if (s->stop) (void)hipHostFree(s->stop);
+    if (s->alive) (void)hipHostFree(s->alive);
     if (s->pool) (void)hipHostFree(s->pool);
     if (s->ran) (void)hipEventDestroy(s->ran);
     if (s->run) (void)hipStreamDestroy(s->run);
@@ -1083,7 +1087,9 @@ int server_ensure_running(dls_server *s) {
         if (q == hipErrorNotReady) return DLS_OK;
         if (q != hipSuccess) return hip_fail(q, DLS_EDEVICE);
     }
-    hipError_t e = dlsk::launch_serve(s->args);
+    // a fresh grid: no wave inside a job, the gate open
+    hipError_t e = hipMemsetAsync(s->gate, 0, sizeof(uint64_t), s->run);
+    if (e == hipSuccess) e = dlsk::launch_serve(s->args);
     if (e == hipSuccess) e = hipEventRecord(s->ran, s->run);
     if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
     s->launched = true;
@@ -1148,7 +1154,11 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     s->max_jobs = max_jobs;
     s->pool_bytes = (pool_bytes + 15) & ~int64_t(15);
     s->variant = variant;
-    bool ok = hipMalloc((void **)&s->state, sizeof(dlsk::JobState) * max_jobs) == hipSuccess;
+    const size_t state_bytes = sizeof(dlsk::JobState) * max_jobs;
+    s->waves = ds->cus * bpc * 4;
+    bool ok = hipMalloc((void **)&s->state, state_bytes + 256) == hipSuccess;
+    if (ok) s->gate = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(s->state) + state_bytes);
+    ok = ok && hipHostMalloc((void **)&s->alive, sizeof(uint32_t) * s->waves, hipHostMallocCoherent) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&s->jobs, sizeof(dlsk::JobDesc) * max_jobs, hipHostMallocCoherent) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&s->done, sizeof(dlsk::JobDone) * max_jobs, hipHostMallocCoherent) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&s->stop, sizeof(uint32_t) * 64, hipHostMallocCoherent) == hipSuccess;
@@ -1157,8 +1167,10 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
         server_release(s);
         return DLS_ENOMEM;
     }
-    s->device_bytes = sizeof(dlsk::JobState) * max_jobs;
-    s->pinned_bytes = (sizeof(dlsk::JobDesc) + sizeof(dlsk::JobDone)) * max_jobs + 256 + (size_t)s->pool_bytes;
+    s->device_bytes = state_bytes + 256;
+    s->pinned_bytes = (sizeof(dlsk::JobDesc) + sizeof(dlsk::JobDone)) * max_jobs + 256 + (size_t)s->pool_bytes +
+                      sizeof(uint32_t) * s->waves;
+    std::memset(s->alive, 0, sizeof(uint32_t) * s->waves);
     std::memset(s->jobs, 0, sizeof(dlsk::JobDesc) * max_jobs);
     std::memset(s->done, 0, sizeof(dlsk::JobDone) * max_jobs);
     std::memset(s->stop, 0, sizeof(uint32_t) * 64);
@@ -1166,7 +1178,7 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     // is ever queued on it, and it never waits for the null stream
     hipError_t e = hipStreamCreateWithFlags(&s->run, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ran, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMemsetAsync(s->state, 0, sizeof(dlsk::JobState) * max_jobs, s->run);
+    if (e == hipSuccess) e = hipMemsetAsync(s->state, 0, state_bytes + 256, s->run);
     if (e == hipSuccess) e = hipStreamSynchronize(s->run);
     if (e != hipSuccess) {
         const int r = hip_fail(e, DLS_EDEVICE);
@@ -1186,6 +1198,8 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     a.pool = s->pool;
     a.stop = s->stop;
     a.published = reinterpret_cast<const uint64_t *>(s->stop + 32);  // its own cache line
+    a.gate = s->gate;
+    a.alive = s->alive;
     a.idle_ticks = 100000000ull / 20;  // 50 ms at 100 MHz
     a.refill_every = refill + (refill & 1);
     a.chunk = chunk;
@@ -1309,6 +1323,15 @@ int dls_server_info(dls_server *s, int64_t *allocated_bytes, int64_t *pool_free,
     if (pool_free) *pool_free = s->pool_free;
     if (slots_free) *slots_free = (int)s->free_slots.size();
     if (launches) *launches = s->launches;
+    return DLS_OK;
+}
+
+int dls_server_waves(dls_server *s, int *live_out, int *grid_out) {
+    if (!s) return DLS_EINVAL;
+    int live = 0;
+    for (int w = 0; w < s->waves; ++w) live += __atomic_load_n(&s->alive[w], __ATOMIC_RELAXED) ? 1 : 0;
+    if (live_out) *live_out = live;
+    if (grid_out) *grid_out = s->waves;
     return DLS_OK;
 }
 

@@ -1823,9 +1823,20 @@ __global__ void __launch_bounds__(256) valu_probe(int iters, uint32_t *sink) {
 // the job's outstanding counter; the piece that takes it to zero writes the
 // job's result to host-pinned memory.  A wave whose job has nothing left to
 // take moves, when all its lanes are idle, to the oldest published job that
-// has; a wave that finds none for idle_ticks (or sees the stop flag) leaves.
-// Waves of different jobs -- and of different orders -- run side by side, so
-// jobs that arrive while others run are taken as soon as waves free up.
+// has.  Waves of different jobs -- and of different orders -- run side by
+// side, so jobs that arrive while others run are taken as soon as waves free
+// up.
+//
+// The grid leaves as a whole, never wave by wave: a gate word counts the
+// waves inside a job, and a wave that has found no job for idle_ticks closes
+// the gate only while that count is zero (one compare-and-swap from 0 to the
+// closing bit); a wave enters a job by adding one and goes on only if the
+// closing bit was clear.  Once closed, every wave leaves at its next look,
+// and the host launches the grid again for the next job.  (Were
+// waves to leave one by one, a grid that had thinned out during a long job's
+// tail would keep serving every later job with the few waves left, and the
+// host, seeing the kernel still running, would not launch it again.)  The
+// stop flag ends every wave that is not inside a job.
 //
 // LDS per wave: its descriptor table, the first level's 4-byte descriptor and
 // pattern of the job (for building records), its lanes' stacks (one row of
@@ -2013,9 +2024,15 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
             if (my_id >= 0) {
                 // the workunit's cells from the pool (16-byte loads), then its record
                 uint32_t words[PS / 4];
-                const uint32_t *src = reinterpret_cast<const uint32_t *>(pre + (size_t)my_id * PS);
+                const uint4 *src = reinterpret_cast<const uint4 *>(pre + (size_t)my_id * PS);
 #pragma unroll
-                for (int q = 0; q < PS / 4; ++q) words[q] = hload32(src + q);
+                for (int q = 0; q < PS / 16; ++q) {
+                    const uint4 v = src[q];
+                    words[4 * q] = v.x;
+                    words[4 * q + 1] = v.y;
+                    words[4 * q + 2] = v.z;
+                    words[4 * q + 3] = v.w;
+                }
                 uint64_t c0 = 0;
                 bool mis = false;
                 const R r = prefix_record<N, VS>(words, patbits, desc0, nlev, 0u, &c0, &mis);
@@ -2066,18 +2083,35 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     }
 }
 
+// Host-ring reads are rationed: every read of host-pinned memory is a
+// round trip over the host link, which the running jobs' workunit reads
+// share.  One wave at a time, at most once per kServePollTicks, reads the
+// host's publish word; only when it has moved since the last scan does that
+// wave read the ring's pub words, and it sets up every new job it finds.
+// Every other wave finds jobs in the device-side work states alone.
+constexpr uint64_t kServePollTicks = 500;  // 5 us at 100 MHz
+
 // The oldest published job that has untaken workunits: its slot, or -1;
-// *pub_out gets its pub word.  Jobs already set up are found in the
-// device-side work states; the host-pinned ring is read only when the host's
-// publish counter has moved since this wave last looked (*seen), and a job
-// found there is set up by the first wave that claims it.  Whether a job is
-// takeable is judged from the claim word alone (job number and size in one
-// word), the same word serve_job works from.
-__device__ __forceinline__ int serve_pick(const ServeArgs &a, int lane, uint64_t now, uint64_t *seen,
-                                          uint64_t *pub_out) {
-    const uint64_t pubc = hload64(a.published);
-    const bool fresh = pubc != *seen;
-    *seen = pubc;
+// *pub_out gets its pub word.  A job found in the ring is set up by the
+// first wave that claims it.  Whether a job is takeable is judged from the
+// claim word alone (job number and size in one word), the same word
+// serve_job works from.
+__device__ __forceinline__ int serve_pick(const ServeArgs &a, int lane, uint64_t now, uint64_t *pub_out) {
+    uint64_t *last_poll = a.gate + 1;  // device: tick of the last look at the publish word
+    uint64_t *scanned = a.gate + 2;    // device: publish word at the last ring scan
+    bool fresh = false;
+    uint64_t pubc = 0;
+    if (lane == 0) {
+        uint64_t t = __hip_atomic_load(last_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (now - t >= kServePollTicks &&
+            __hip_atomic_compare_exchange_strong(last_poll, &t, now, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+            pubc = hload64(a.published);
+            fresh = pubc != __hip_atomic_load(scanned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    fresh = __builtin_amdgcn_readlane((int)fresh, 0) != 0;
+    pubc = bcast64(pubc, 0);
     uint64_t best = ~0ull, best_claim = 0;
     for (int j = lane; j < a.max_jobs; j += 64) {
         JobState *js = &a.state[j];
@@ -2106,6 +2140,9 @@ __device__ __forceinline__ int serve_pick(const ServeArgs &a, int lane, uint64_t
             }
         }
     }
+    // a later scan starts from here (a scan that ends after a newer one
+    // stores an older word, which only makes the next poller scan again)
+    if (fresh && lane == 0) __hip_atomic_store(scanned, pubc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t mine = best;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -2123,20 +2160,34 @@ __global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     unsigned char *wsm = smem + (threadIdx.x >> 6) * kSvWave;  // this wave's LDS
+    uint32_t *alive = a.alive + blockIdx.x * (kSvBlock / 64) + (threadIdx.x >> 6);
+    if (lane == 0) __hip_atomic_store(alive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
     uint32_t backoff = 1;
-    uint64_t seen = ~0ull;  // publish counter at this wave's last look at the ring
     uint32_t empty = 0;     // picks in a row that gave the wave no workunit
     for (;;) {
+        if (__hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kServeClosing) break;
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
         uint64_t pub = 0;
-        const int slot = serve_pick(a, lane, now, &seen, &pub);
+        const int slot = serve_pick(a, lane, now, &pub);
         if (slot >= 0 && empty < 16) {
-            // the descriptor and cells of the job (written by the host before
-            // its pub word) are used only while the slot still holds it
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            // enter: one more wave inside a job; a wave that finds the grid
+            // leaving takes its count back and leaves too (the closing bit
+            // stays set: it was set while the count was zero)
+            bool in = false;
+            if (lane == 0) {
+                const uint64_t g = __hip_atomic_fetch_add(a.gate, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                in = !(g & kServeClosing);
+                if (!in) __hip_atomic_fetch_add(a.gate, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!__builtin_amdgcn_readlane((int)in, 0)) break;
+            // the descriptor and cells of the job are used only while the
+            // slot still holds it: reading its pub word from the ring, then
+            // an acquire fence, orders them after the host's writes (made
+            // before its release store of that word)
             bool took = false;
             if (hload64(&a.jobs[slot].pub) == pub) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
                 const int n = (int)hload32(&a.jobs[slot].n);
                 const bool vs = hload32(&a.jobs[slot].vs) != 0u;
                 switch (n * 2 + (vs ? 1 : 0)) {
@@ -2148,6 +2199,7 @@ __global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1
                     default: break;  // the host publishes only these orders
                 }
             }
+            if (lane == 0) __hip_atomic_fetch_add(a.gate, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // -1
             if (took) {
                 empty = 0;
                 idle_since = __builtin_amdgcn_s_memrealtime();
@@ -2158,13 +2210,25 @@ __global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1
         } else {
             empty = 0;
         }
-        // nothing taken: the stop flag and the idle limit end the wave
-        const bool stop = hload32(a.stop) != 0u;
-        if (stop || now - idle_since > a.idle_ticks) break;
+        // nothing taken: the stop flag ends the wave; past the idle limit the
+        // wave closes the gate for the whole grid if no wave is inside a job
+        if (hload32(a.stop) != 0u) break;
+        if (now - idle_since > a.idle_ticks) {
+            bool closed = false;
+            if (lane == 0) {
+                uint64_t g = __hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (g == 0u)
+                    __hip_atomic_compare_exchange_strong(a.gate, &g, kServeClosing, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                closed = (g == 0u) || (g & kServeClosing);  // g: 0 on success, else the value found
+            }
+            if (__builtin_amdgcn_readlane((int)closed, 0)) break;
+        }
         // an idle wave looks again after 1, 2, 4, ... up to about 100 us
         for (uint32_t t = 0; t < backoff; ++t) __builtin_amdgcn_s_sleep(32);
         backoff = backoff < 128 ? backoff * 2 : 128;
     }
+    if (lane == 0) __hip_atomic_store(alive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 hipError_t launch_serve(const ServeArgs &a) {

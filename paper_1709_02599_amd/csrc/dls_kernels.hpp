@@ -148,7 +148,9 @@ struct ServeArgs {
     const uint8_t *pool;    // host-pinned prefixes
     const uint32_t *stop;   // host-pinned: nonzero = leave when idle
     const uint64_t *published;  // host-pinned: seq of the last job published
-    uint64_t idle_ticks;    // a wave with no job for this long leaves
+    uint64_t *gate;         // device: waves inside a job | kServeClosing (zero at launch)
+    uint32_t *alive;        // host-pinned: one word per wave of the grid, 1 while it runs
+    uint64_t idle_ticks;    // the grid leaves once a wave has found no job for this long and none is busy
     int refill_every;
     int chunk;              // tasks a wave takes from a job at once
     hipStream_t stream;
@@ -157,6 +159,7 @@ struct ServeArgs {
 constexpr int kServeMinN = 4;
 constexpr int kServeMaxN = 9;
 constexpr int kServeMaxJobs = 256;
+constexpr uint64_t kServeClosing = 1ull << 63;  // gate bit: the grid is leaving
 // bytes of one workunit in the prefix pool (n*n cells, padded for 16-byte loads)
 inline int pre_stride(int n) { return (n * n + 15) & ~15; }
 hipError_t launch_serve(const ServeArgs &a);

@@ -181,3 +181,56 @@ def test_server_argument_errors():
         assert ei.value.code == -2
     finally:
         dls.dls_server_destroy(h)
+
+
+def _wait(h, ticket, limit_s):
+    t_end = time.time() + limit_s
+    while True:
+        done, c, ticks = dls.dls_server_poll(h, ticket)
+        if done:
+            return c, ticks
+        assert time.time() < t_end, "request not done"
+        time.sleep(0.0005)
+
+
+def test_grid_stays_whole_while_a_long_job_runs():
+    # A long request split into few workunits keeps a few waves busy; the
+    # rest of the grid has nothing to take for longer than the idle limit
+    # (50 ms) but stays, so requests submitted meanwhile are served by the
+    # whole grid and finish long before the long one.  Once nothing runs,
+    # the grid leaves as a whole.
+    n = 8
+    units = dls.dls_split_target(n, 0, oracle.identity_prefix(n), 400, 24)
+    counts = dls.dls_count(n, 0, units)
+    pick = int(np.argmin(np.abs(np.log(np.maximum(counts, 1).astype(np.float64)) - np.log(5e6))))
+    long_prefix, long_count = units[pick], int(counts[pick])
+    assert 1e6 <= long_count <= 5e7, long_count
+    small = _requests(16, seed=13, k_range=(12, 20))
+    want = _oracle(small)
+    h = dls.dls_server_create(max_jobs=64, pool_bytes=16 << 20)
+    try:
+        t_long = dls.dls_server_submit(h, n, 0, long_prefix, 64)
+        t0 = time.time()
+        time.sleep(0.2)
+        live, grid = dls.dls_server_waves(h)
+        done_early = dls.dls_server_poll(h, t_long)[0]
+        print(f"long job: count {long_count}; after 0.2 s: {live}/{grid} waves live, done={done_early}", flush=True)
+        assert not done_early, "the long job must outlast the idle limit for this test to mean anything"
+        assert live == grid
+        tickets = [(q, dls.dls_server_submit(h, q.n, dls.DLS_VSYM if q.vs else 0, q.prefix, 512)) for q in small]
+        ends = []
+        for q, t in tickets:
+            c, ticks = _wait(h, t, 30)
+            assert c == want[q.rid], (q.rid, q.n, q.vs)
+            ends.append(ticks[1])
+        t_small = time.time() - t0
+        c, ticks = _wait(h, t_long, 120)
+        t_all = time.time() - t0
+        print(f"small requests done after {t_small:.3f} s, long one after {t_all:.3f} s", flush=True)
+        assert c == long_count
+        assert max(e for e in ends if e) < ticks[1]
+        assert dls.dls_server_info(h)["launches"] == 1
+        time.sleep(0.3)                  # longer than the idle limit: the grid leaves as a whole
+        assert dls.dls_server_waves(h)[0] == 0
+    finally:
+        dls.dls_server_destroy(h)
