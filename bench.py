@@ -64,7 +64,7 @@ OPS_PER_TASK = 3
 
 
 LAUNCH_FIELDS = ("block", "blocks_per_cu", "refill_every", "order_variant", "expand_target", "chunk_min",
-                 "steal_depth", "lds_masks", "refill_min")
+                 "steal_depth", "lds_masks", "refill_min", "wg_pool")
 
 
 def tuned_launch(n, flags, workload):

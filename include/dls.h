@@ -252,6 +252,13 @@ typedef struct {
     int refill_min;     /* persistent kernel: while static tasks remain, a
                            wave refills its idle lanes when at least this
                            many are idle (1..64; 0 = default 8)           */
+    int wg_pool;        /* persistent kernel, line masks in VGPRs, no
+                           donation across the chip: once the static queue
+                           is empty, the waves of a workgroup share subtrees
+                           through a pool of at most this many task records
+                           in LDS (as many as fit in half the record area);
+                           0 = default (on, as many as fit), negative = off
+                           (each wave shares only among its own lanes)     */
 } dls_launch;
 
 /*

@@ -49,7 +49,7 @@ class DlsLaunch(ctypes.Structure):
                 ("steal_depth", ctypes.c_int), ("refill_every", ctypes.c_int),
                 ("order_variant", ctypes.c_int), ("time_kernel", ctypes.c_int),
                 ("expand_target", ctypes.c_int), ("chunk_min", ctypes.c_int), ("lds_masks", ctypes.c_int),
-                ("refill_min", ctypes.c_int)]
+                ("refill_min", ctypes.c_int), ("wg_pool", ctypes.c_int)]
 
 
 def _load() -> ctypes.CDLL:

@@ -72,7 +72,7 @@ def best(n: int, flags: int, workload: str, arch: Optional[str] = None) -> Optio
 
 
 FIELDS = ("block", "blocks_per_cu", "steal_depth", "refill_every", "order_variant", "time_kernel",
-          "expand_target", "chunk_min", "lds_masks", "refill_min")
+          "expand_target", "chunk_min", "lds_masks", "refill_min", "wg_pool")
 
 
 def _launch(settings: dict, time_kernel: int = 0) -> DlsLaunch:
@@ -216,6 +216,14 @@ def main(argv=None):
         r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
                  space={**{k: (v,) for k, v in second.items() if k not in ("refill_every", "refill_min")},
                         "refill_every": (16, 32, 64, 128), "refill_min": (1, 2, 4, 8, 16, 32)},
+                 default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1}, save=False)
+        third = {k: v for k, v in r["best"].items() if k != "ms"}
+        # stage 4: the workgroup pool of the tail (on / off) against the
+        # workgroup size, grid and smallest chunk
+        r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
+                 space={**{k: (v,) for k, v in third.items() if k not in ("block", "blocks_per_cu", "chunk_min")},
+                        "wg_pool": (0, -1), "block": (256, 512), "blocks_per_cu": (0, 8, 16),
+                        "chunk_min": (4, 16, 64)},
                  default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1})
         print(json.dumps({"workload": "order8-symbreak-row1", "best": r["best"], "default": r["default"],
                           "plain_ms": r["plain_ms"]}), flush=True)

@@ -437,6 +437,8 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
         a.tune.steal_depth = sd;
         a.tune.refill_min = (launch && launch->refill_min) ? launch->refill_min : 8;
         if (a.tune.refill_min < 1 || a.tune.refill_min > 64) return DLS_EINVAL;
+        // the workgroup pool: the kernel caps it at what fits
+        a.tune.wg_pool = (launch && launch->wg_pool) ? (launch->wg_pool < 0 ? 0 : launch->wg_pool) : (1 << 20);
         a.tune.donate_max = 2;
         a.tune.donate_low = 256;
         a.tune.tail_poll = 4;

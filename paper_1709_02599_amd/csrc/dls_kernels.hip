@@ -939,6 +939,17 @@ constexpr uint64_t kStallTicks = 100000000ull * 20;
 // expcnt (bits 6:4 = 7) or lgkmcnt (bits 11:8 = 15)
 constexpr int kWaitVm0 = 0x0F70;
 
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x);
+
+// The workgroup pool of the persistent kernel's tail (line masks in VGPRs):
+// the record area after the stacks holds one record per thread; its first
+// half is a 32-record mailbox per wave (sharing inside a wave), the second
+// half the pool: a header (lock, record count, then idle and busy lanes of
+// each of up to 16 waves) and the pooled records.
+constexpr uint32_t kPoolHeader = 256u;
+constexpr int kPoolIdle = 2, kPoolBusy = 18;  // word offsets in the header
+constexpr uint32_t kMailbox = 32u;            // records per wave
+
 template <int N, bool VS, bool STATS, bool LM>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) persistent_kernel(const Plan plan, const Rec<N, VS> *recs, int64_t num,
                                                           uint64_t *counts, uint32_t *status, uint64_t *steps,
@@ -976,9 +987,33 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     const int lim = tune.steal_depth > 0 ? nlev - tune.steal_depth : 0;
     const uint64_t total_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
 
-    // Work moves between waves only with global donation; without it a wave
-    // whose lanes are all idle once the static queue is empty just leaves.
+    // Work moves between the waves of the chip only with global donation;
+    // without it, work moves between the waves of a workgroup through the
+    // workgroup pool (line masks in VGPRs), and a wave whose lanes are all
+    // idle once the static queue is empty leaves when no wave of its
+    // workgroup has work left (or at once, without the pool).
     const bool global = cap > 0 && lim > 0;
+    // (the pool's addresses are recomputed where used: kept live across the
+    // search loop they would cost registers)
+    auto rec_area = [&]() { return smem + vl_stacks_end(VLaneDesc<N, VS>::rows(nlev), blockDim.x, sizeof(S)); };
+    auto pool_hdr_of = [&]() {
+        return reinterpret_cast<uint32_t *>(rec_area() + sizeof(Rec<N, VS>) * blockDim.x / 2);
+    };
+    auto pool_cap_of = [&]() -> int {
+        if (LM || global || tune.wg_pool <= 0) return 0;
+        const int room = (int)((sizeof(Rec<N, VS>) * blockDim.x / 2 - kPoolHeader) / sizeof(Rec<N, VS>));
+        return tune.wg_pool < room ? tune.wg_pool : room;
+    };
+    if (pool_cap_of() > 0) {
+        // every wave counts as busy until it reaches the tail
+        uint32_t *pool_hdr = pool_hdr_of();
+        if (threadIdx.x < 2) pool_hdr[threadIdx.x] = 0u;
+        if (threadIdx.x < 16) {
+            pool_hdr[kPoolIdle + threadIdx.x] = 0u;
+            pool_hdr[kPoolBusy + threadIdx.x] = threadIdx.x < (blockDim.x >> 6) ? 64u : 0u;
+        }
+        __syncthreads();
+    }
     // this wave counts as busy from its start until it finds no work anywhere
     if (global && lane == 0) atomicAdd((unsigned long long *)&ctrl->busy, 1ull);
     bool marked = global;
@@ -1115,22 +1150,23 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
         // busy lanes hand the untried siblings at their shallowest open level
         // to idle lanes of the same wave, as task records (any number per
         // round)
-        if (want && want != ~0ull) {
-            int lvl = -1;
-            if (has && !L.done()) {
-                const int dep = L.depth(dbase);
-                const int top = dep < last - 1 ? dep : last - 1;
-                for (int l = L.start_level(dbase); l < top; ++l) {
-                    const uint32_t sv = *slot_of(l);
-                    if (sv & (sv - 1u)) {
-                        lvl = l;
-                        break;
-                    }
+        int lvl = -1;  // this lane's shallowest open level, or -1
+        if (want != ~0ull && (want || pool_cap_of() > 0) && has && !L.done()) {
+            const int dep = L.depth(dbase);
+            const int top = dep < last - 1 ? dep : last - 1;
+            for (int l = L.start_level(dbase); l < top; ++l) {
+                const uint32_t sv = *slot_of(l);
+                if (sv & (sv - 1u)) {
+                    lvl = l;
+                    break;
                 }
             }
+        }
+        if (want && want != ~0ull) {
             const uint64_t donors = __ballot(lvl >= 0);
             const uint64_t nd = (uint64_t)__popcll(donors), ni = (uint64_t)__popcll(want);
-            const uint64_t m = nd < ni ? nd : ni;
+            uint64_t m = nd < ni ? nd : ni;
+            if (!LM) m = m < kMailbox ? m : kMailbox;
             if (m) {
                 const uint64_t drank = (uint64_t)__popcll(donors & below);
                 const uint64_t rrank = (uint64_t)__popcll(want & below);
@@ -1145,9 +1181,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                     got = shfl_words(r, src);
                 } else {
                     // through the wave's LDS mailbox (cheaper in registers)
-                    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(
-                                           smem + vl_stacks_end(VLaneDesc<N, VS>::rows(nlev), blockDim.x, sizeof(S))) +
-                                       (threadIdx.x & ~63u);
+                    Rec<N, VS> *mbox = reinterpret_cast<Rec<N, VS> *>(rec_area()) + (threadIdx.x >> 6) * kMailbox;
                     if (lvl >= 0 && drank < m) mbox[drank] = give(lvl);
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                     __builtin_amdgcn_wave_barrier();
@@ -1160,8 +1194,94 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                     stored = 0;
                     has = true;
                 }
+                if (drank < m) lvl = -1;  // its open level went to a lane of this wave
                 want = __ballot(!has);
             }
+        }
+        if (pool_cap_of() > 0) {
+            // ---------------- share work inside the workgroup ----------------
+            const int pool_cap = pool_cap_of();
+            uint32_t *const pool_hdr = pool_hdr_of();
+            Rec<N, VS> *const pool_rec =
+                reinterpret_cast<Rec<N, VS> *>(reinterpret_cast<unsigned char *>(pool_hdr) + kPoolHeader);
+            const uint32_t my_wave = threadIdx.x >> 6;
+            const uint32_t nwaves = blockDim.x >> 6;
+            // Each wave publishes its idle and busy lanes.  A wave with idle
+            // lanes takes pooled records; a wave whose donors kept their open
+            // level (no idle lane of its own left for them) pools it while the
+            // other waves have more idle lanes than records are pooled.  The
+            // pool is guarded by a lock word; its holder is a wave of this
+            // workgroup, resident and never waiting inside the lock.
+            const uint32_t nidle = (uint32_t)__popcll(want);
+            if (lane == 0) {
+                __hip_atomic_store(&pool_hdr[kPoolIdle + my_wave], nidle, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(&pool_hdr[kPoolBusy + my_wave], 64u - nidle, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            uint32_t hungry = 0;
+            if (lane < (int)nwaves && lane != (int)my_wave)
+                hungry = __hip_atomic_load(&pool_hdr[kPoolIdle + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            hungry = (uint32_t)wave_sum64(hungry);
+            const uint32_t pcount = (uint32_t)__builtin_amdgcn_readfirstlane(
+                (int)__hip_atomic_load(&pool_hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            const bool take_round = want && pcount > 0;
+            if (!(hungry > pcount && pcount < (uint32_t)pool_cap)) lvl = -1;
+            const uint64_t donors = take_round ? 0ull : __ballot(lvl >= 0);
+            if (take_round || donors) {
+                if (lane == 0) {
+                    while (atomicCAS(&pool_hdr[0], 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)pool_hdr[1]);
+                if (take_round) {
+                    // the idle lane of rank k takes the k-th of the top m records
+                    const uint32_t m = nidle < cnt ? nidle : cnt;
+                    const uint32_t rrank = (uint32_t)__popcll(want & below);
+                    const bool take = !has && rrank < m;
+                    Rec<N, VS> got;
+                    if (take) got = pool_rec[cnt - m + rrank];
+                    cnt -= m;
+                    if (take) {
+                        start(got);
+                        out = &counts[got.origin];
+                        stored = 0;
+                        has = true;
+                    }
+                } else {
+                    uint32_t q = hungry > cnt ? hungry - cnt : 0u;
+                    const uint32_t room = (uint32_t)pool_cap - cnt;
+                    q = q < room ? q : room;
+                    const uint32_t drank = (uint32_t)__popcll(donors & below);
+                    if (lvl >= 0 && drank < q) pool_rec[cnt + drank] = give(lvl);
+                    const uint32_t nd = (uint32_t)__popcll(donors);
+                    cnt += nd < q ? nd : q;
+                }
+                if (lane == 0) pool_hdr[1] = cnt;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) __hip_atomic_store(&pool_hdr[0], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                want = __ballot(!has);
+            }
+            if (want == ~0ull) {
+                // all lanes idle: leave once no other wave of the workgroup has
+                // busy lanes and nothing is pooled, else look again shortly
+                uint32_t b = 0;
+                if (lane < (int)nwaves && lane != (int)my_wave)
+                    b = __hip_atomic_load(&pool_hdr[kPoolBusy + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const uint32_t left = (uint32_t)wave_sum64(b) +
+                                      __hip_atomic_load(&pool_hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (__builtin_amdgcn_readfirstlane((int)left) == 0) {
+                    if (lane == 0)
+                        __hip_atomic_store(&pool_hdr[kPoolIdle + my_wave], 0u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            continue;
         }
         if (!global) {
             if (want == ~0ull) break;

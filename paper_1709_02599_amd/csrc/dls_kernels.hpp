@@ -65,6 +65,7 @@ struct Tuning {
     int tail_poll;     // tail: read the queue state every tail_poll passes (power of 2)
     int chunk_min;     // smallest static chunk a wave takes from the queue
     int lds_masks;     // nonzero: row and column masks in LDS (LdsLane) instead of VGPRs
+    int wg_pool;       // tail, VGPR layout: records the waves of a workgroup pool in LDS (0 = off)
 };
 
 // Size in bytes of one task record (packed masks of a partial square plus

@@ -205,7 +205,10 @@ def test_grid_stays_whole_while_a_long_job_runs():
     pick = int(np.argmin(np.abs(np.log(np.maximum(counts, 1).astype(np.float64)) - np.log(5e6))))
     long_prefix, long_count = units[pick], int(counts[pick])
     assert 1e6 <= long_count <= 5e7, long_count
-    small = _requests(16, seed=13, k_range=(12, 20))
+    # orders 7 and 8: their oracle counts take well under a second
+    from paper_1709_02599_amd.serve import Request
+    small = [Request(j.jid, j.n, j.vs, j.prefix, 0.0)
+             for j in dls_workloads.job_stream(16, 1000.0, seed=13, orders=(7, 8), k_range=(14, 20))]
     want = _oracle(small)
     h = dls.dls_server_create(max_jobs=64, pool_bytes=16 << 20)
     try:
