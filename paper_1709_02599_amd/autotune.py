@@ -215,7 +215,7 @@ def main(argv=None):
         # stage 3: refill cadence against the refill trigger
         r = tune(8, 0, pre, "order8-symbreak-row1", reps=args.reps,
                  space={**{k: (v,) for k, v in second.items() if k not in ("refill_every", "refill_min")},
-                        "refill_every": (16, 32, 64, 128), "refill_min": (1, 2, 4, 8, 16, 32)},
+                        "refill_every": (32, 64, 96, 128), "refill_min": (1, 2, 4, 8, 16, 32)},
                  default={"order_variant": 0, "block": 256, "refill_every": 32, "lds_masks": -1}, save=False)
         third = {k: v for k, v in r["best"].items() if k != "ms"}
         # stage 4: the workgroup pool of the tail (on / off) against the

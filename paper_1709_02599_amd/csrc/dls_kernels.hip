@@ -950,7 +950,9 @@ constexpr uint32_t kPoolHeader = 256u;
 constexpr int kPoolIdle = 2, kPoolBusy = 18;  // word offsets in the header
 constexpr uint32_t kMailbox = 32u;            // records per wave
 
-template <int N, bool VS, bool STATS, bool LM>
+// GL: donation across the chip compiled in (small batches); without it the
+// kernel carries none of that code, which keeps its register use down.
+template <int N, bool VS, bool STATS, bool LM, bool GL>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) persistent_kernel(const Plan plan, const Rec<N, VS> *recs, int64_t num,
                                                           uint64_t *counts, uint32_t *status, uint64_t *steps,
                                                           Ctrl *ctrl, Rec<N, VS> *items, uint32_t *ready,
@@ -992,7 +994,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     // workgroup pool (line masks in VGPRs), and a wave whose lanes are all
     // idle once the static queue is empty leaves when no wave of its
     // workgroup has work left (or at once, without the pool).
-    const bool global = cap > 0 && lim > 0;
+    const bool global = GL && cap > 0 && lim > 0;
     // (the pool's addresses are recomputed where used: kept live across the
     // search loop they would cost registers)
     auto rec_area = [&]() { return smem + vl_stacks_end(VLaneDesc<N, VS>::rows(nlev), blockDim.x, sizeof(S)); };
@@ -2398,16 +2400,20 @@ static hipError_t launch_n(const LaunchArgs &a) {
         }
         // the state after the last pass
         const Expand *ex = expand ? a.ex + (a.epasses & 1) : nullptr;
-#define DLS_PERSISTENT(STATS, LM)                                                                              \
-    hipLaunchKernelGGL((persistent_kernel<N, VS, STATS, LM>), dim3(a.grid), dim3(block), lds, a.stream, a.plan, recs, \
-                       a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune, ex)
+        const bool gl = a.item_cap > 0 && a.tune.steal_depth > 0;
+#define DLS_PERSISTENT(STATS, LM, GL)                                                                          \
+    hipLaunchKernelGGL((persistent_kernel<N, VS, STATS, LM, GL>), dim3(a.grid), dim3(block), lds, a.stream, a.plan, \
+                       recs, a.num, a.counts, a.status, a.steps, a.ctrl, items, a.ready, a.item_cap, a.tune, ex)
+#define DLS_PERSISTENT_GL(STATS, LM) \
+    if (gl) DLS_PERSISTENT(STATS, LM, true); else DLS_PERSISTENT(STATS, LM, false);
         if (a.tune.lds_masks) {
-            if (a.steps) DLS_PERSISTENT(true, true);
-            else DLS_PERSISTENT(false, true);
+            if (a.steps) { DLS_PERSISTENT_GL(true, true) }
+            else { DLS_PERSISTENT_GL(false, true) }
         } else {
-            if (a.steps) DLS_PERSISTENT(true, false);
-            else DLS_PERSISTENT(false, false);
+            if (a.steps) { DLS_PERSISTENT_GL(true, false) }
+            else { DLS_PERSISTENT_GL(false, false) }
         }
+#undef DLS_PERSISTENT_GL
 #undef DLS_PERSISTENT
         if (expand) hipLaunchKernelGGL(ex_scatter, dim3(kExBlocks), dim3(256), 0, a.stream, ex, a.counts);
     } else {
