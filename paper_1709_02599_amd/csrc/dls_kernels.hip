@@ -840,6 +840,22 @@ __global__ void __launch_bounds__(256) prep_kernel(const Plan plan, const uint8_
     counts[idx] = count;
 }
 
+// Byte offset of thread tid's stack slot within a level row of the
+// search kernels' stacks (nthreads slots of `size` bytes).  With the
+// lanes side by side, four lanes share each 4-byte word, and lanes at
+// different levels meet in the same bank.  Instead the words are dealt out
+// per lane: the slots of one wave's 64 lanes fall in 64 consecutive words --
+// one per LDS bank, whatever level each lane is at -- and the threads sharing
+// a word belong to different waves.  A row stays nthreads * size bytes when
+// the waves fill the words (a multiple of 4 / size waves); otherwise the
+// plain order is kept.
+__device__ __forceinline__ uint32_t stack_slot(uint32_t tid, uint32_t nthreads, uint32_t size) {
+    const uint32_t per = 4u / size;  // threads per word
+    if ((nthreads >> 6) % per) return tid * size;
+    const uint32_t wave = tid >> 6, lane = tid & 63u;
+    return ((wave / per) * 64u + lane) * 4u + (wave % per) * size;
+}
+
 // ---------------------------------------------------------------------------
 // plain kernel: one task per lane, run to completion
 // ---------------------------------------------------------------------------
@@ -862,7 +878,7 @@ __global__ void __launch_bounds__(1024) plain_kernel(const Plan plan, const Rec<
     if (live) {
         const Rec<N, VS> r = recs[idx];
         const uint32_t dbase = lds_of(smem);
-        const uint32_t lane_off = dbase + kStackBase + threadIdx.x * (uint32_t)sizeof(S);
+        const uint32_t lane_off = dbase + kStackBase + stack_slot(threadIdx.x, blockDim.x, (uint32_t)sizeof(S));
         const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
         const uint32_t da_last = dbase + 4u * (uint32_t)(nlev - 1);
         Lane<N, VS> L;
@@ -979,7 +995,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     const uint64_t below = (1ull << lane) - 1ull;
     const uint32_t dbase = lds_of(smem);
     const uint32_t sbase = LM ? lm_stack_base(LINES, nlev, blockDim.x, VS) : kVlStackBase;
-    const uint32_t loff = sbase + threadIdx.x * (uint32_t)sizeof(S);  // from smem
+    const uint32_t loff = sbase + stack_slot(threadIdx.x, blockDim.x, (uint32_t)sizeof(S));  // from smem
     const uint32_t lane_off = dbase + loff;                             // LDS address
     const uint32_t stride = blockDim.x * (uint32_t)sizeof(S);
     auto slot_of = [&](int l) -> S * { return reinterpret_cast<S *>(smem + (loff + (uint32_t)l * stride)); };
