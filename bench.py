@@ -238,7 +238,11 @@ def main():
 
     # ---------------- measured integer VALU peak ----------------
     # 8 independent chains of xor / add / rotate per lane: 24 VALU
-    # instructions per iteration, all 2048 lanes per CU resident
+    # instructions per iteration, all 2048 lanes per CU resident.  The
+    # hardware counter SQ_INSTS_VALU of the probe dispatch reads exactly
+    # 24 x iterations x waves, so 24 is the issued count; the rate it
+    # sustains is above the 16 lanes x 2.4 GHz per SIMD of the nominal
+    # peak, which is why `frac` (against the nominal) is the lower figure.
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     pblocks, piters = cus * 8, 20000
     sink = torch.zeros(pblocks * 256, dtype=torch.int32, device=dev)
