@@ -243,8 +243,9 @@ def main(argv=None):
     if want("order8-diag14"):
         spre, _ = dls_split(8, 0, 14)
         s = tune(8, 0, spre, "order8-diag14",
-                 space={"order_variant": (0, 1, 5), "refill_every": (32, 64), "blocks_per_cu": (0, 16),
-                        "refill_min": (4, 8), "chunk_min": (0, 16)},
+                 space={"order_variant": (1, 5), "refill_every": (64, 128), "block": (256, 512),
+                        "blocks_per_cu": (0, 8, 16), "refill_min": (1, 2, 4), "chunk_min": (16,),
+                        "wg_pool": (0, -1)},
                  default={"order_variant": 0, "refill_every": 32, "blocks_per_cu": 0, "refill_min": 8,
                           "chunk_min": 0}, reps=1)
         print(json.dumps({"workload": "order8-diag14", "best": s["best"], "default": s["default"]}), flush=True)
@@ -258,7 +259,8 @@ def main(argv=None):
         p9, _ = dls_split(9, DLS_SYMBREAK, 22)
         pos = np.array(dls_workloads.sample_positions(len(p9), 1500, seed=7), dtype=np.int64)
         s = tune(9, 0, np.ascontiguousarray(p9[pos]), "order9-sample",
-                 space={"order_variant": (0, 2, 5), "refill_every": (32, 64, 128)},
+                 space={"order_variant": (0, 2, 5), "refill_every": (32, 64, 128), "lds_masks": (0, -1),
+                        "wg_pool": (0, -1)},
                  default={"order_variant": 0, "refill_every": 32}, reps=1, plain=False)
         print(json.dumps({"workload": "order9-sample", "best": s["best"], "default": s["default"]}), flush=True)
 

@@ -176,7 +176,7 @@ def latency_stats(results: List[Result]) -> dict:
     return out
 
 
-def sweep(jobs: int = 200, fractions=(0.25, 0.5, 0.75, 0.9), seed: Optional[int] = None,
+def sweep(jobs: int = 200, fractions=(0.25, 0.5, 0.75, 0.9, 1.1), seed: Optional[int] = None,
           server: Optional[Server] = None, emit=print) -> List[dict]:
     """Closed-loop capacity first (all requests waiting), then Poisson
     arrivals at fractions of it; one dict per rate."""
@@ -228,7 +228,7 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=200)
-    ap.add_argument("--fractions", default="0.25,0.5,0.75,0.9")
+    ap.add_argument("--fractions", default="0.25,0.5,0.75,0.9,1.1")
     ap.add_argument("--min-tasks", type=int, default=16384)
     ap.add_argument("--blocks-per-cu", type=int, default=2)
     args = ap.parse_args(argv)
