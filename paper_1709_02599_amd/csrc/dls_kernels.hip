@@ -572,11 +572,15 @@ struct VLane {
         const uint32_t nda = (uint32_t)max((int)(da + (up ? 0u - DB : DB)), (int)da0);
         const uint32_t nsa = __umul24(nda, kst) + sc0;
         const Desc nd = DT::load(nda);
+        // the descriptor of the level whose value changes (the new level
+        // going up, the current one going down): one more LDS read instead
+        // of selecting its fields in registers
+        const Desc td = DT::load(up ? nda : da);
         const uint32_t saved = lds_ld<S>(nsa);
         lds_st<S>(sa, (S)cand);  // up lanes write 0 into a slot nobody reads again
         const uint32_t stored = up ? saved : cand;
         const uint32_t b = stored & (0u - stored);
-        toggle(up ? nd : cur, b);
+        toggle(td, b);
         if constexpr (DW) {
             // a square is counted on reaching the sentinel (increment 1);
             // both candidate sets are formed and one is kept by a mask, so
@@ -596,7 +600,6 @@ struct VLane {
                 cand = up ? (stored ^ b) : (leaf ? 0u : nc);
             }
         }
-        cur = nd;
         da = nda;
         sa = nsa;
     }
