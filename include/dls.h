@@ -216,7 +216,10 @@ int dls_stream_status(void *stream, uint32_t *status_out);
 
 /* Launch shape for the *_ex calls; zero fields mean "library default". */
 typedef struct {
-    int block;          /* threads per workgroup (64..1024, multiple of 64)   */
+    int block;          /* threads per workgroup (64..1024, multiple of 64);
+                           halved while the workgroup's LDS would exceed
+                           what the device allows a workgroup (160 KiB on
+                           gfx950)                                         */
     int blocks_per_cu;  /* persistent kernel: workgroups per CU in the grid
                            (0 = 2048 / block).  Workgroups beyond those that
                            fit at once start when others leave; they still

@@ -136,6 +136,7 @@ static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 struct DeviceState {
     bool init = false;
     int cus = 0;
+    size_t lds_max = 64 * 1024;         // LDS a workgroup may use (160 KiB on gfx950)
     unsigned char *scratch = nullptr;   // device address of `scratch` on this device
     std::map<void *, QueueSlot> slots;  // scratch and work queue per stream
     std::map<int, CanonTables> canon;   // per order
@@ -166,6 +167,7 @@ int device_state(DeviceState **out, int *dev_out) {
         hipError_t e1 = hipGetDeviceProperties(&prop, dev);
         if (e1 != hipSuccess) return hip_fail(e1, DLS_EDEVICE);
         ds.cus = prop.multiProcessorCount;
+        if (prop.sharedMemPerBlock > 0) ds.lds_max = prop.sharedMemPerBlock;
         void *sp = nullptr;
         hipError_t e2 = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
         if (e2 != hipSuccess) return hip_fail(e2, DLS_EDEVICE);
@@ -363,8 +365,8 @@ int count_async_impl(int n, uint32_t flags, const uint8_t *pattern, const uint8_
     // layout needs two words per kind (measured 21-27 % faster there); at
     // N <= 8 the faster layout depends on the workload (autotuner)
     const bool lm = a.persistent && ((launch && launch->lds_masks) ? launch->lds_masks > 0 : n >= 9);
-    while (block > 64 && dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent, lm) > 64 * 1024) block /= 2;
-    if (dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent, lm) > 64 * 1024) return DLS_EINVAL;
+    while (block > 64 && dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent, lm) > ds->lds_max) block /= 2;
+    if (dlsk::lds_bytes(n, vs, a.plan.nlev, block, a.persistent, lm) > ds->lds_max) return DLS_EINVAL;
     a.tune.lds_masks = lm ? 1 : 0;
     a.block = block;
     const size_t rb = dlsk::record_bytes(n, vs);

@@ -213,10 +213,26 @@ def test_order8_symbreak_counts(order8_symbreak, plain):
 
 def test_order8_symbreak_tuned_launch_counts(order8_symbreak):
     # the launch the benchmark times (fill-order variant 5, VGPR masks,
-    # 16 workgroups of 256 per CU, refill every 64 steps, chunks >= 16)
+    # 8 workgroups of 512 per CU, refill every 64 steps when two lanes are
+    # idle, chunks >= 64, the workgroup pool of the tail on)
     pre, mult, opre, omult, a, b, ocounts = order8_symbreak
-    launch = {"block": 256, "blocks_per_cu": 16, "refill_every": 64, "order_variant": 5,
-              "chunk_min": 16, "lds_masks": -1}
+    launch = {"block": 512, "blocks_per_cu": 8, "refill_every": 64, "order_variant": 5,
+              "chunk_min": 64, "lds_masks": -1, "refill_min": 2}
+    c, st = gpu_counts(dls, 8, 0, pre, launch=launch)
+    assert st == 0
+    assert np.array_equal(c[a], ocounts[b])
+
+
+@pytest.mark.parametrize("block", [64, 128, 1024])
+@pytest.mark.parametrize("wg_pool", [0, -1, 3])
+def test_order8_symbreak_workgroup_pool(order8_symbreak, block, wg_pool):
+    # the tail's workgroup pool on (as many records as fit, or only 3),
+    # and off, for 1, 2 and 16 waves per workgroup (the stack slots are
+    # dealt out per bank only when the waves fill the words: not at 64 or
+    # 128 lanes with byte slots); every count against the oracle
+    pre, mult, opre, omult, a, b, ocounts = order8_symbreak
+    launch = {"block": block, "blocks_per_cu": max(1, 2048 // block), "refill_every": 32,
+              "order_variant": 5, "lds_masks": -1, "wg_pool": wg_pool}
     c, st = gpu_counts(dls, 8, 0, pre, launch=launch)
     assert st == 0
     assert np.array_equal(c[a], ocounts[b])
