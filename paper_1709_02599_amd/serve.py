@@ -221,6 +221,40 @@ def sweep(jobs: int = 200, fractions=(0.25, 0.5, 0.75, 0.9, 1.1), seed: Optional
     return rows
 
 
+def solo_times(jobs: int = 200, min_tasks: int = 16384, seed: Optional[int] = None) -> dict:
+    """Each request of the stream counted alone by the batch path (its
+    workunits from dls_split_target, one dls_count_async_ex launch timed with
+    the library's kernel events): the search work the mix holds, to compare
+    with the serving kernel's latencies."""
+    import os
+    import sys
+    import torch
+    from . import DlsLaunch, dls_count_async_ex, dls_kernel_time_ms, dls_split_target
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import dls_workloads
+    seed = dls_workloads.DEFAULT_SEED if seed is None else seed
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for j in dls_workloads.job_stream(jobs, 1.0, seed=seed):
+        flags = DLS_VSYM if j.vs else 0
+        units = dls_split_target(j.n, flags, j.prefix, min_tasks, 24)
+        if len(units) == 0:
+            continue
+        pattern = (units[0] != EMPTY).astype(np.uint8)
+        d_pre = torch.from_numpy(np.ascontiguousarray(units)).to(dev)
+        d_cnt = torch.zeros(len(units), dtype=torch.int64, device=dev)
+        d_st = torch.zeros(1, dtype=torch.int32, device=dev)
+        dls_count_async_ex(j.n, flags, pattern, d_pre, len(units), d_cnt, d_st, stream, DlsLaunch(time_kernel=1))
+        torch.cuda.synchronize()
+        ms, _ = dls_kernel_time_ms(stream)
+        rows.append({"rid": j.jid, "n": j.n, "vs": bool(j.vs), "workunits": len(units), "kernel_ms": ms,
+                     "count": int(d_cnt.sum().item())})
+    rows.sort(key=lambda r: -r["kernel_ms"])
+    return {"requests_searched": len(rows), "total_kernel_ms": sum(r["kernel_ms"] for r in rows),
+            "largest": rows[:5]}
+
+
 def main(argv=None):
     """Rate sweep; prints one JSON line per rate."""
     import argparse
@@ -231,7 +265,12 @@ def main(argv=None):
     ap.add_argument("--fractions", default="0.25,0.5,0.75,0.9,1.1")
     ap.add_argument("--min-tasks", type=int, default=16384)
     ap.add_argument("--blocks-per-cu", type=int, default=2)
+    ap.add_argument("--solo", action="store_true",
+                    help="instead of the sweep: each request counted alone by the batch path")
     args = ap.parse_args(argv)
+    if args.solo:
+        print(json.dumps(solo_times(args.jobs, args.min_tasks)), flush=True)
+        return
     with Server(min_tasks=args.min_tasks, launch={"blocks_per_cu": args.blocks_per_cu}) as srv:
         sweep(args.jobs, [float(x) for x in args.fractions.split(",")], server=srv,
               emit=lambda row: print(json.dumps(row), flush=True))
