@@ -384,7 +384,16 @@ int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream);
  * run is served at once.  The kernel keeps each job's outstanding pieces
  * and computes its total (the exact count of the request, the definition of
  * Sec. 1) on the device; the piece that finishes a job writes its result to
- * host-pinned memory, read by dls_server_poll.  The grid leaves as a whole:
+ * host-pinned memory, read by dls_server_poll.  A wave takes about the
+ * job's workunits over twice the grid's waves at a time, so even a small job
+ * spreads over the grid, and its lanes share subtrees among themselves (the
+ * split of Sec. 5.2 done on the device).  With steal_depth > 0, a wave with
+ * fewer than 8 idle lanes also hands the untried siblings of a shallow level
+ * (more than steal_depth levels above the last) to the job's donation queue
+ * in device memory while waves that found no work are waiting (a ring of
+ * 2048 records per job; while it is full, waves keep their work), and each
+ * such wave takes one and shares it among its lanes.  The grid leaves as a
+ * whole:
  * once a wave has found no job for 50 ms while no wave is inside a job, every
  * wave leaves, and the next submit or poll launches the kernel again; while
  * any job runs, every wave of the grid stays (none leaves on its own).
@@ -392,9 +401,15 @@ int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream);
 typedef struct dls_server dls_server;
 
 /* launch (may be NULL): blocks_per_cu (1 or 2 workgroups of 256 per CU;
- * default 2), refill_every (default 64), chunk_min = workunits a wave takes
- * from a job at once (default 4), order_variant (fill order); block 0 or
- * 256; other fields ignored.  A request is split at most 24 cells deep.
+ * default 2), refill_every (default 64), chunk_min = most workunits a wave
+ * takes from a job at once (default 64; a wave takes about the job's
+ * workunits over twice the grid's waves, at least one), order_variant (fill
+ * order), steal_depth
+ * (> 0: hand subtrees between waves as above; 0 or negative: off, the
+ * default -- measured slower on the serving mix); block 0 or 256; other
+ * fields ignored.  The donation rings take
+ * 144 KiB of device memory per job slot.  A request is split at most 24
+ * cells deep.
  * DLS_EINVAL for bad arguments, DLS_ENOMEM. */
 int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch, dls_server **out);
 
@@ -428,6 +443,11 @@ int dls_server_info(dls_server *s, int64_t *allocated_bytes, int64_t *pool_free,
  * NULL).  While the kernel runs, *live_out equals *grid_out except while the
  * grid starts or leaves.  DLS_EINVAL for a NULL server. */
 int dls_server_waves(dls_server *s, int *live_out, int *grid_out);
+
+/* Subtrees handed between waves through the jobs' donation queues, summed
+ * over the requests retired so far by dls_server_poll.  DLS_EINVAL for a
+ * NULL argument. */
+int dls_server_shared(dls_server *s, int64_t *subtrees_out);
 
 /* Stops the kernel (bounded wait) and frees everything.  Requests not polled
  * done are dropped.  DLS_EDEVICE if the kernel did not stop (the server's

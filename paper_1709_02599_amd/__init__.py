@@ -23,7 +23,7 @@ __all__ = [
     "dls_order_variant", "dls_reduce_weighted", "dls_kernel_time_ms", "dls_count_cells",
     "dls_count_cells_async", "dls_split_cells", "dls_order_cost",
     "dls_hourglass_classes_async", "hourglass_classes_gpu", "DLS_EBUSY", "dls_server_create",
-    "dls_server_submit", "dls_server_poll", "dls_server_info", "dls_server_waves", "dls_server_destroy",
+    "dls_server_submit", "dls_server_poll", "dls_server_info", "dls_server_waves", "dls_server_shared", "dls_server_destroy",
     "dls_split_target",
 ]
 
@@ -125,6 +125,7 @@ def _load() -> ctypes.CDLL:
         "dls_server_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]),
         "dls_server_waves": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "dls_server_shared": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64)]),
         "dls_server_destroy": (ctypes.c_int, [vp]),
         "dls_split_target": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, u8p, ctypes.c_int64, ctypes.c_int, u8p,
                                             ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
@@ -495,6 +496,14 @@ def dls_server_waves(server: int) -> tuple:
     _check(_lib.dls_server_waves(ctypes.c_void_p(server), ctypes.byref(live), ctypes.byref(grid)),
            "dls_server_waves")
     return int(live.value), int(grid.value)
+
+
+def dls_server_shared(server: int) -> int:
+    """Subtrees handed between waves through the jobs' donation queues,
+    over the requests retired so far."""
+    k = ctypes.c_int64(0)
+    _check(_lib.dls_server_shared(ctypes.c_void_p(server), ctypes.byref(k)), "dls_server_shared")
+    return int(k.value)
 
 
 def dls_server_destroy(server: int) -> None:

@@ -1046,8 +1046,11 @@ struct dls_server {
     bool launched = false;
     int64_t launches = 0;
     dlsk::JobDesc *jobs = nullptr;  // host-pinned
-    dlsk::JobState *state = nullptr;  // followed by the gate word (device)
+    dlsk::JobState *state = nullptr;  // followed by the gate words (device)
     uint64_t *gate = nullptr;
+    uint8_t *items = nullptr;       // device: donation queues, kServeItems records per slot
+    uint64_t *ready = nullptr;      // device: their ready words
+    int64_t shared = 0;             // subtrees handed between waves, over the jobs retired
     dlsk::JobDone *done = nullptr;  // host-pinned
     uint32_t *stop = nullptr;       // host-pinned
     uint32_t *alive = nullptr;      // host-pinned: one word per wave of the grid
@@ -1074,6 +1077,8 @@ namespace {
 
 void server_release(dls_server *s) {
     if (s->state) (void)hipFree(s->state);
+    if (s->items) (void)hipFree(s->items);
+    if (s->ready) (void)hipFree(s->ready);
     if (s->jobs) (void)hipHostFree(s->jobs);
     if (s->done) (void)hipHostFree(s->done);
     if (s->stop) (void)hipHostFree(s->stop);
@@ -1091,8 +1096,8 @@ int server_ensure_running(dls_server *s) {
         if (q == hipErrorNotReady) return DLS_OK;
         if (q != hipSuccess) return hip_fail(q, DLS_EDEVICE);
     }
-    // a fresh grid: no wave inside a job, the gate open
-    hipError_t e = hipMemsetAsync(s->gate, 0, sizeof(uint64_t), s->run);
+    // a fresh grid: no wave inside a job or asking for work, the gate open
+    hipError_t e = hipMemsetAsync(s->gate, 0, 4 * sizeof(uint64_t), s->run);
     if (e == hipSuccess) e = dlsk::launch_serve(s->args);
     if (e == hipSuccess) e = hipEventRecord(s->ran, s->run);
     if (e != hipSuccess) return hip_fail(e, DLS_EDEVICE);
@@ -1144,7 +1149,8 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     const int variant = launch ? launch->order_variant : 0;
     const int bpc = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 2;
     const int refill = (launch && launch->refill_every) ? launch->refill_every : 64;
-    const int chunk = (launch && launch->chunk_min) ? launch->chunk_min : 4;
+    const int chunk = (launch && launch->chunk_min) ? launch->chunk_min : 64;
+    const int steal = launch ? launch->steal_depth : 0;
     if (variant < 0 || variant >= dls::kOrderVariants || bpc < 1 || bpc > 2 || refill < 2 || chunk < 1 ||
         chunk > 65536 || (launch && launch->block && launch->block != 256))
         return DLS_EINVAL;
@@ -1162,6 +1168,10 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     s->waves = ds->cus * bpc * 4;
     bool ok = hipMalloc((void **)&s->state, state_bytes + 256) == hipSuccess;
     if (ok) s->gate = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(s->state) + state_bytes);
+    const size_t item_bytes = (size_t)max_jobs * dlsk::kServeItems * dlsk::kServeItemBytes;
+    const size_t ready_bytes = (size_t)max_jobs * dlsk::kServeItems * sizeof(uint64_t);
+    ok = ok && hipMalloc((void **)&s->items, item_bytes) == hipSuccess;
+    ok = ok && hipMalloc((void **)&s->ready, ready_bytes) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&s->alive, sizeof(uint32_t) * s->waves, hipHostMallocCoherent) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&s->jobs, sizeof(dlsk::JobDesc) * max_jobs, hipHostMallocCoherent) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&s->done, sizeof(dlsk::JobDone) * max_jobs, hipHostMallocCoherent) == hipSuccess;
@@ -1171,7 +1181,7 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
         server_release(s);
         return DLS_ENOMEM;
     }
-    s->device_bytes = state_bytes + 256;
+    s->device_bytes = state_bytes + 256 + item_bytes + ready_bytes;
     s->pinned_bytes = (sizeof(dlsk::JobDesc) + sizeof(dlsk::JobDone)) * max_jobs + 256 + (size_t)s->pool_bytes +
                       sizeof(uint32_t) * s->waves;
     std::memset(s->alive, 0, sizeof(uint32_t) * s->waves);
@@ -1183,6 +1193,7 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     hipError_t e = hipStreamCreateWithFlags(&s->run, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ran, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemsetAsync(s->state, 0, state_bytes + 256, s->run);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ready, 0, ready_bytes, s->run);
     if (e == hipSuccess) e = hipStreamSynchronize(s->run);
     if (e != hipSuccess) {
         const int r = hip_fail(e, DLS_EDEVICE);
@@ -1203,6 +1214,9 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     a.stop = s->stop;
     a.published = reinterpret_cast<const uint64_t *>(s->stop + 32);  // its own cache line
     a.gate = s->gate;
+    a.items = s->items;
+    a.ready = s->ready;
+    a.steal_depth = steal;
     a.alive = s->alive;
     a.idle_ticks = 100000000ull / 20;  // 50 ms at 100 MHz
     a.refill_every = refill + (refill & 1);
@@ -1297,6 +1311,7 @@ int dls_server_poll(dls_server *s, int64_t ticket, uint64_t *count_out, uint64_t
             j.count = __atomic_load_n(&d->total, __ATOMIC_RELAXED);
             j.t0 = __atomic_load_n(&d->t_start, __ATOMIC_RELAXED);
             j.t1 = __atomic_load_n(&d->t_end, __ATOMIC_RELAXED);
+            s->shared += (int64_t)__atomic_load_n(&d->shared, __ATOMIC_RELAXED);
             j.done = true;
             server_give_range(s, j.off, j.len);
             s->free_slots.push_back(j.slot);
@@ -1336,6 +1351,13 @@ int dls_server_waves(dls_server *s, int *live_out, int *grid_out) {
     for (int w = 0; w < s->waves; ++w) live += __atomic_load_n(&s->alive[w], __ATOMIC_RELAXED) ? 1 : 0;
     if (live_out) *live_out = live;
     if (grid_out) *grid_out = s->waves;
+    return DLS_OK;
+}
+
+int dls_server_shared(dls_server *s, int64_t *subtrees_out) {
+    if (!s || !subtrees_out) return DLS_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *subtrees_out = s->shared;
     return DLS_OK;
 }
 

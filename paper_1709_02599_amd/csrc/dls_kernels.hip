@@ -1988,6 +1988,13 @@ constexpr uint32_t kSvStacks = 82u * 128u;  // (81 + 1) rows x 64 lanes x 2 byte
 constexpr uint32_t kSvMbox = 64u * 48u;     // 64 records of order 9
 constexpr uint32_t kSvWave = kSvTable + kSvInfo + kSvStacks + kSvMbox;
 constexpr int kSvBlock = 256;
+constexpr uint32_t kSvPoll = 4;   // passes between a full wave's looks at the donation queue
+constexpr int kSvShareMin = 8;    // idle lanes that start sharing inside a wave
+// Subtrees a wave hands on per look: one.  A lane that reserves record q
+// waits until record q - kServeItems of the same entry is read; were two
+// lanes of one wave to reserve q - kServeItems and q in the same pass, the
+// second would wait for a record its own wave has not yet written.
+constexpr int kSvDonate = 1;
 static_assert(kSvWave % 16 == 0, "per-wave LDS regions keep 16-byte alignment");
 
 // system-scope loads of the host-pinned ring (no cached copy is ever used)
@@ -2013,6 +2020,7 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     static_assert(DB * (uint32_t)(NN + 1) <= kSvTable, "descriptor table");
     static_assert((uint32_t)(NN + 1) * 64u * sizeof(S) <= kSvStacks, "stacks");
     static_assert(64u * sizeof(R) <= kSvMbox, "mailbox");
+    static_assert(sizeof(R) <= (size_t)kServeItemBytes, "donation record");
     const uint64_t below = (1ull << lane) - 1ull;
     const JobDesc *jd = &a.jobs[slot];
     JobState *js = &a.state[slot];
@@ -2027,6 +2035,17 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     JobDone *done_rec = &a.done[slot];
     const int last = nlev - 1;
     const uint8_t *pre = a.pool + (int64_t)hload64(&jd->pre_off);
+    // the job's donation queue, a ring of kServeItems records: record q
+    // lives in entry q % kServeItems; the entry's ready word holds
+    // job number << 32 | (2 x lap + 1) once record q (lap q / kServeItems)
+    // is written and 2 x lap + 2 once it is read, so an entry is refilled
+    // only after its previous record of the same job was read
+    R *items = reinterpret_cast<R *>(a.items + (size_t)slot * ((size_t)kServeItems * kServeItemBytes));
+    uint64_t *ready = a.ready + (size_t)slot * kServeItems;
+    const uint64_t tag = seq32 << 32;
+    // donated subtrees start above this level (off unless steal_depth > 0)
+    const int lim = a.steal_depth > 0 ? nlev - a.steal_depth : 0;
+    uint32_t tick = 0;
 
     // the job's plan into this wave's LDS: descriptor table, pattern, first level
     const uint32_t dbase = lds_of(wsm);
@@ -2053,6 +2072,19 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     const uint32_t kst = stride / DB;
     const uint32_t sc0 = lane_off - dbase * kst;
     auto slot_of = [&](int l) -> S * { return reinterpret_cast<S *>(wsm + (loff + (uint32_t)l * stride)); };
+    // the shallowest level in [from, top) whose stack entry still holds
+    // more than one candidate, or -1: eight independent LDS reads at a time
+    auto open_level = [&](int from, int top) -> int {
+        for (int l0 = from; l0 < top; l0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = l0 + u < top ? (uint32_t)*slot_of(l0 + u) : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (v[u] & (v[u] - 1u)) return l0 + u;
+        }
+        return -1;
+    };
     R *mbox = reinterpret_cast<R *>(wsm + kSvTable + kSvInfo + kSvStacks);
     const uint32_t da_last = dbase + DB * (uint32_t)(last > 0 ? last : 0);
     lds_st<S>(lane_off, (S)0);
@@ -2078,7 +2110,16 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     bool has = false;
     bool job_left = true;
     bool took = false;
-    uint64_t cb = 0, ce = 0;
+    // Pieces of the job this wave holds (workunits and records it took) and
+    // each lane's squares over them: released together once every lane is
+    // idle.  Subtrees shared among the wave's own lanes stay inside those
+    // pieces and cost no atomic.
+    uint64_t own = 0;
+    uint64_t acc = 0;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / 64u);
+    uint64_t share = (uint64_t)ntasks / (2u * nwaves);
+    share = share < chunk ? share : chunk;
+    share = share > 1u ? share : 1u;
     auto start = [&](const R &r) {
         L.from_rec(r, dbase, last, lane_off, stride);
         lds_st<S>(L.sa, (S)0);
@@ -2093,74 +2134,156 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
         }
         L.flush();
         if (has && L.done()) {
-            // The piece's count goes into the job's total, then one piece
-            // less is outstanding.  Both are device-scope atomics performed
-            // where every wave's atomics meet; the decrement's operand depends
-            // on the add's result, so the add is done before the decrement is
-            // issued, and the piece that takes the counter to zero finds
-            // every piece's count in the total (no cache write-back or
-            // invalidation on this path).
-            const uint64_t prev =
-                __hip_atomic_fetch_add(&js->total, L.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // -1, computed from the add's result (a total never reaches 2^64 - 1)
-            const uint64_t dec = prev == ~0ull ? 0ull : ~0ull;
-            const uint64_t left =
-                __hip_atomic_fetch_add(&js->remaining, dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (left == 1) {
-                // the job's last piece: its result to host-pinned memory
-                JobDone *d = done_rec;
-                const uint64_t tot = __hip_atomic_fetch_add(&js->total, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t ts = __hip_atomic_load(&js->t_start, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&d->total, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&d->t_start, ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&d->t_end, (uint64_t)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&d->pub, pub, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
-            has = false;
+            acc += L.cnt;
             L.cnt = 0;
+            has = false;
         }
         uint64_t want = __ballot(!has);
+        if (want == ~0ull && own) {
+            // Every lane is idle: all the work of the pieces this wave took is
+            // done.  Their count goes into the job's total, then `own` pieces
+            // less are outstanding.  Both are device-scope atomics performed
+            // where every wave's atomics meet; the decrement's operand depends
+            // on the add's result, so the add is done before the decrement is
+            // issued, and the wave that takes the counter to zero finds every
+            // piece's count in the total (no cache write-back or invalidation
+            // on this path).
+            const uint64_t sum = wave_sum64(acc);
+            acc = 0;
+            if (lane == 0) {
+                const uint64_t prev =
+                    __hip_atomic_fetch_add(&js->total, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // -own, computed from the add's result (a total never reaches 2^64 - 1)
+                const uint64_t dec = prev == ~0ull ? 0ull : 0ull - own;
+                const uint64_t left =
+                    __hip_atomic_fetch_add(&js->remaining, dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (left == own) {
+                    // the job's last pieces: its result to host-pinned memory
+                    JobDone *d = done_rec;
+                    const uint64_t tot =
+                        __hip_atomic_fetch_add(&js->total, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t ts = __hip_atomic_load(&js->t_start, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t nr =
+                        __hip_atomic_load(&js->dq_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 0xFFFFFFFFull;
+                    __hip_atomic_store(&d->shared, nr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(&d->total, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(&d->t_start, ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(&d->t_end, (uint64_t)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(&d->pub, pub, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+            }
+            own = 0;
+        }
+
+        // ---------------- a full wave gives subtrees to waves without work ----------------
+        // Every kSvPoll passes a wave with fewer than kSvShareMin idle lanes
+        // (it shares inside itself from that many on) compares the
+        // number of waves that found no work with the records waiting in the
+        // job's queue; for the difference (at most kSvDonate per wave and
+        // look) its lanes hand on the untried siblings at their shallowest
+        // open level above the cut-off.  A lane reserves record q only while
+        // fewer than kServeItems records are reserved and untaken (so record
+        // q - kServeItems, in the same entry, is taken; its taker reads it
+        // in the same pass).  A record is one more outstanding piece before
+        // it is published, and its ready word carries the job number, so a
+        // taker never reads a record of another job.
+        if (__popcll(want) < kSvShareMin && lim > 0 && ((++tick) & (kSvPoll - 1)) == 0) {
+            uint64_t hungry = 0, queued = ~0ull;
+            if (lane == 0) {
+                hungry = __hip_atomic_load(a.gate + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (hungry) {
+                    const uint64_t r = __hip_atomic_load(&js->dq_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t h = __hip_atomic_load(&js->dq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t rl = r & 0xFFFFFFFFull, hl = h & 0xFFFFFFFFull;
+                    if ((r >> 32) == seq32 && (h >> 32) == seq32 && rl >= hl) queued = rl - hl;
+                }
+            }
+            hungry = bcast64(hungry, 0);
+            queued = bcast64(queued, 0);
+            if (queued != ~0ull && hungry > queued) {
+                int lvl = -1;
+                if (has && !L.done()) {
+                    const int dep = L.depth(dbase);
+                    lvl = open_level(L.start_level(dbase), dep < lim ? dep : lim);
+                }
+                const uint64_t donors = __ballot(lvl >= 0);
+                uint64_t quota = hungry - queued;
+                quota = quota < (uint64_t)kSvDonate ? quota : (uint64_t)kSvDonate;
+                if (lvl >= 0 && (uint64_t)__popcll(donors & below) < quota) {
+                    uint64_t r = __hip_atomic_load(&js->dq_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bool got = false;
+                    for (int tries = 0; tries < 8; ++tries) {
+                        const uint64_t h = __hip_atomic_load(&js->dq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((r >> 32) != seq32 || (h >> 32) != seq32) break;
+                        if ((r & 0xFFFFFFFFull) - (h & 0xFFFFFFFFull) >= (uint64_t)kServeItems) break;  // full
+                        if (__hip_atomic_compare_exchange_strong(&js->dq_res, &r, r + 1ull, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            got = true;
+                            break;
+                        }
+                    }
+                    if (got) {
+                        const uint64_t q = r & 0xFFFFFFFFull;
+                        const uint64_t e = q % (uint64_t)kServeItems, lap = q / (uint64_t)kServeItems;
+                        // the entry's record of the previous lap has been taken; wait until it is read
+                        bool free = lap == 0;
+                        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                        while (!free) {
+                            free = __hip_atomic_load(&ready[e], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+                                   (tag | (2ull * lap));
+                            if (free || __builtin_amdgcn_s_memrealtime() - t0 > kStallTicks) break;
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        // a record never published stays outstanding: the job is then never reported done
+                        if (free) {
+                            __hip_atomic_fetch_add(&js->remaining, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            items[e] = L.donate(lvl, dbase, slot_of, 0u);
+                            __hip_atomic_store(&ready[e], tag | (2ull * lap + 1ull), __ATOMIC_RELEASE,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
+        }
 
         // ---------------- idle lanes take workunits of the job ----------------
+        // A wave takes at most `share` workunits per pass (about the job's
+        // workunits over twice the grid's waves, at most `chunk`), so a job
+        // spreads over the whole grid; its own sharing then fills the rest
+        // of its lanes.  One compare-and-swap claims them: it checks the job
+        // number in the same word, so a wave never claims workunits of a
+        // later job in the same slot.
+        int64_t my_id = -1;
         if (want && job_left) {
             const uint64_t k = (uint64_t)__popcll(want);
             const uint64_t rank = (uint64_t)__popcll(want & below);
             const int leader = __ffsll((unsigned long long)want) - 1;
-            int64_t my_id = -1;
-            uint64_t given = 0;
-            while (given < k) {
-                if (cb >= ce) {
-                    uint64_t got = 0, b0 = 0;
-                    if (lane == leader) {
-                        uint64_t h = __hip_atomic_load(&js->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        for (int tries = 0; tries < 64; ++tries) {
-                            const uint64_t taken = h & 0xFFFFFFFFull;
-                            if ((h >> 32) != seq32 || taken >= (uint64_t)ntasks) break;
-                            const uint64_t rem = (uint64_t)ntasks - taken;
-                            const uint64_t sz = rem < chunk ? rem : chunk;
-                            if (__hip_atomic_compare_exchange_strong(&js->head, &h, h + sz, __ATOMIC_RELAXED,
-                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                                got = sz;
-                                b0 = taken;
-                                break;
-                            }
-                        }
-                    }
-                    got = bcast64(got, leader);
-                    b0 = bcast64(b0, leader);
-                    if (!got) {
-                        job_left = false;
+            const uint64_t ask = k < share ? k : share;
+            uint64_t got = 0, b0 = 0;
+            if (lane == leader) {
+                uint64_t h = __hip_atomic_load(&js->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int tries = 0; tries < 64; ++tries) {
+                    const uint64_t taken = h & 0xFFFFFFFFull;
+                    if ((h >> 32) != seq32 || taken >= (uint64_t)ntasks) break;
+                    const uint64_t rem = (uint64_t)ntasks - taken;
+                    const uint64_t sz = rem < ask ? rem : ask;
+                    if (__hip_atomic_compare_exchange_strong(&js->head, &h, h + sz, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        got = sz;
+                        b0 = taken;
                         break;
                     }
-                    cb = b0;
-                    ce = b0 + got;
-                    took = true;
                 }
-                const uint64_t take = (k - given) < (ce - cb) ? (k - given) : (ce - cb);
-                if (!has && rank >= given && rank < given + take) my_id = (int64_t)(cb + (rank - given));
-                cb += take;
-                given += take;
+            }
+            got = bcast64(got, leader);
+            b0 = bcast64(b0, leader);
+            if (!got) {
+                job_left = false;
+            } else {
+                took = true;
+                own += got;
+                if (!has && rank < got) my_id = (int64_t)(b0 + rank);
             }
             if (my_id >= 0) {
                 // the workunit's cells from the pool (16-byte loads), then its record
@@ -2184,26 +2307,19 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
             want = __ballot(!has);
         }
 
-        // ---------------- nothing left to take: share subtrees inside the wave ----------------
-        if (want && want != ~0ull && !job_left) {
+        // ---------------- idle lanes share the busy lanes' subtrees inside the wave ----------------
+        // once at least kSvShareMin lanes are idle, or the busy ones are few
+        const int nidle = __popcll(want);
+        if (want && want != ~0ull && (nidle >= kSvShareMin || 64 - nidle < kSvShareMin)) {
             int lvl = -1;
             if (has && !L.done()) {
                 const int dep = L.depth(dbase);
-                const int top = dep < last - 1 ? dep : last - 1;
-                for (int l = L.start_level(dbase); l < top; ++l) {
-                    const uint32_t sv = *slot_of(l);
-                    if (sv & (sv - 1u)) {
-                        lvl = l;
-                        break;
-                    }
-                }
+                lvl = open_level(L.start_level(dbase), dep < last - 1 ? dep : last - 1);
             }
             const uint64_t donors = __ballot(lvl >= 0);
             const uint64_t nd = (uint64_t)__popcll(donors), ni = (uint64_t)__popcll(want);
             const uint64_t m = nd < ni ? nd : ni;
             if (m) {
-                // the new pieces are outstanding before any of them can finish
-                if (lane == 0) __hip_atomic_fetch_add(&js->remaining, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint64_t drank = (uint64_t)__popcll(donors & below);
                 const uint64_t rrank = (uint64_t)__popcll(want & below);
                 const bool take = !has && rrank < m;
@@ -2217,6 +2333,59 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
                     start(got);
                     has = true;
                 }
+                want = __ballot(!has);
+            }
+        }
+
+        // ---------------- an idle lane takes a subtree another wave handed on ----------------
+        // by a wave with every lane idle, one record per pass: the wave's own
+        // sharing spreads it over its lanes, and records are handed on for
+        // whole waves
+        if (want == ~0ull && !job_left) {
+            const int leader = __ffsll((unsigned long long)want) - 1;
+            bool got = false;
+            if (lane == leader) {
+                uint64_t h = __hip_atomic_load(&js->dq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int tries = 0; tries < 16; ++tries) {
+                    const uint64_t r = __hip_atomic_load(&js->dq_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((h >> 32) != seq32 || (r >> 32) != seq32) break;
+                    if ((r & 0xFFFFFFFFull) <= (h & 0xFFFFFFFFull)) break;
+                    if (__hip_atomic_compare_exchange_strong(&js->dq_head, &h, h + 1ull, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        got = true;
+                        break;
+                    }
+                }
+                if (got) {
+                    // its donor publishes the record right after reserving it
+                    const uint64_t q = h & 0xFFFFFFFFull;
+                    const uint64_t e = q % (uint64_t)kServeItems, lap = q / (uint64_t)kServeItems;
+                    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                    bool ok = false;
+                    for (;;) {
+                        if (__hip_atomic_load(&ready[e], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+                            (tag | (2ull * lap + 1ull))) {
+                            ok = true;
+                            break;
+                        }
+                        if (__builtin_amdgcn_s_memrealtime() - t0 > kStallTicks) break;
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    // a record never published within the stall limit stays
+                    // outstanding: the job is then never reported done
+                    if (ok) {
+                        const R rec = items[e];
+                        __hip_atomic_store(&ready[e], tag | (2ull * lap + 2ull), __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        start(rec);
+                        has = true;
+                    }
+                }
+            }
+            if (__builtin_amdgcn_readlane((int)got, leader)) {
+                took = true;
+                // the record is this wave's piece once read (the leader was idle)
+                if (__builtin_amdgcn_readlane((int)has, leader)) ++own;
                 want = __ballot(!has);
             }
         }
@@ -2267,13 +2436,22 @@ __device__ __forceinline__ int serve_pick(const ServeArgs &a, int lane, uint64_t
                 __hip_atomic_store(&js->total, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&js->t_start, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&js->remaining, q & 0xFFFFFFFFull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&js->dq_res, q & ~0xFFFFFFFFull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&js->dq_head, q & ~0xFFFFFFFFull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&js->head, q & ~0xFFFFFFFFull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 c = q;
             }
         }
         if (!c) continue;
         const uint64_t h = __hip_atomic_load(&js->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((h >> 32) == (c >> 32) && (h & 0xFFFFFFFFull) < (c & 0xFFFFFFFFull)) {
+        bool open = (h >> 32) == (c >> 32) && (h & 0xFFFFFFFFull) < (c & 0xFFFFFFFFull);
+        if (!open) {
+            // no untaken workunit: records waiting in its donation queue
+            const uint64_t r = __hip_atomic_load(&js->dq_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t d = __hip_atomic_load(&js->dq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            open = (r >> 32) == (c >> 32) && (d >> 32) == (c >> 32) && (r & 0xFFFFFFFFull) > (d & 0xFFFFFFFFull);
+        }
+        if (open) {
             const uint64_t key = ((c >> 32) << 8) | (uint64_t)j;  // oldest first
             if (key < best) {
                 best = key;
@@ -2306,6 +2484,7 @@ __global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1
     uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
     uint32_t backoff = 1;
     uint32_t empty = 0;     // picks in a row that gave the wave no workunit
+    bool asked = false;     // counted in gate[3]: found no work, asks busy waves for subtrees
     for (;;) {
         if (__hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kServeClosing) break;
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
@@ -2322,6 +2501,10 @@ __global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1
                 if (!in) __hip_atomic_fetch_add(a.gate, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (!__builtin_amdgcn_readlane((int)in, 0)) break;
+            if (asked) {
+                if (lane == 0) __hip_atomic_fetch_add(a.gate + 3, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                asked = false;
+            }
             // the descriptor and cells of the job are used only while the
             // slot still holds it: reading its pub word from the ring, then
             // an acquire fence, orders them after the host's writes (made
@@ -2365,10 +2548,15 @@ __global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1
             }
             if (__builtin_amdgcn_readlane((int)closed, 0)) break;
         }
+        if (!asked) {
+            if (lane == 0) __hip_atomic_fetch_add(a.gate + 3, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            asked = true;
+        }
         // an idle wave looks again after 1, 2, 4, ... up to about 100 us
         for (uint32_t t = 0; t < backoff; ++t) __builtin_amdgcn_s_sleep(32);
         backoff = backoff < 128 ? backoff * 2 : 128;
     }
+    if (asked && lane == 0) __hip_atomic_fetch_add(a.gate + 3, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane == 0) __hip_atomic_store(alive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 

@@ -128,7 +128,9 @@ struct JobState {
     uint64_t total;      // squares counted so far
     uint64_t t_start;    // s_memrealtime when the job was first claimed
     uint64_t claim;      // pub word of the job this state was set up for
-    uint64_t pad[11];
+    uint64_t dq_res;     // job number << 32 | donation-queue records reserved
+    uint64_t dq_head;    // job number << 32 | donation-queue records taken
+    uint64_t pad[9];
 };
 
 // Result of a job (host-pinned, one per ring slot); pub is written last.
@@ -137,6 +139,8 @@ struct JobDone {
     uint64_t total;
     uint64_t t_start;  // s_memrealtime ticks (100 MHz)
     uint64_t t_end;
+    uint64_t shared;   // subtrees handed between waves through the job's donation queue
+    uint64_t pad[3];
 };
 
 struct ServeArgs {
@@ -149,11 +153,16 @@ struct ServeArgs {
     const uint8_t *pool;    // host-pinned prefixes
     const uint32_t *stop;   // host-pinned: nonzero = leave when idle
     const uint64_t *published;  // host-pinned: seq of the last job published
-    uint64_t *gate;         // device: waves inside a job | kServeClosing (zero at launch)
+    uint64_t *gate;         // device, zero at launch: [0] waves inside a job | kServeClosing,
+                            // [1] tick of the last ring poll, [2] publish word at the last scan,
+                            // [3] waves that found no work (they ask busy waves for subtrees)
+    uint8_t *items;         // device: a ring of kServeItems donation records of kServeItemBytes per slot
+    uint64_t *ready;        // device: kServeItems words per slot (job number << 32 | record state)
     uint32_t *alive;        // host-pinned: one word per wave of the grid, 1 while it runs
     uint64_t idle_ticks;    // the grid leaves once a wave has found no job for this long and none is busy
     int refill_every;
-    int chunk;              // tasks a wave takes from a job at once
+    int chunk;              // most workunits a wave takes from a job at once
+    int steal_depth;        // > 0: donate subtrees from levels < levels - steal_depth; else no donation
     hipStream_t stream;
 };
 
@@ -161,6 +170,8 @@ constexpr int kServeMinN = 4;
 constexpr int kServeMaxN = 9;
 constexpr int kServeMaxJobs = 256;
 constexpr uint64_t kServeClosing = 1ull << 63;  // gate bit: the grid is leaving
+constexpr int kServeItems = 2048;      // entries of a job's donation ring
+constexpr int kServeItemBytes = 64;    // >= the largest task record (order 9)
 // bytes of one workunit in the prefix pool (n*n cells, padded for 16-byte loads)
 inline int pre_stride(int n) { return (n * n + 15) & ~15; }
 hipError_t launch_serve(const ServeArgs &a);

@@ -33,7 +33,7 @@ from typing import Dict, List, Optional
 import numpy as np
 
 from . import (DLS_VSYM, dls_server_create, dls_server_destroy, dls_server_info, dls_server_poll,
-               dls_server_submit)
+               dls_server_shared, dls_server_submit)
 
 EMPTY = 0xFF
 TICK_S = 1e-8          # s_memrealtime runs at 100 MHz
@@ -79,6 +79,10 @@ class Server:
 
     def info(self) -> dict:
         return dls_server_info(self.handle)
+
+    def shared(self) -> int:
+        """Subtrees handed between waves so far (requests retired)."""
+        return dls_server_shared(self.handle)
 
     def close(self) -> None:
         if self.handle:
@@ -195,24 +199,27 @@ def sweep(jobs: int = 200, fractions=(0.25, 0.5, 0.75, 0.9, 1.1), seed: Optional
     try:
         srv.run(requests(1.0, seed + 1)[:16], realtime=False)          # warm-up
         reqs = requests(1.0, seed)
+        sh = srv.shared()
         t = time.perf_counter()
         res = srv.run(reqs, realtime=False)
         wall = time.perf_counter() - t
         cap = len(res) / wall
         row = {"mode": "closed-loop", "jobs": len(res), "seconds": wall, "jobs_per_s": cap,
                "squares_per_s": sum(r.count for r in res) / wall, "max_concurrency": max_concurrency(res),
-               **latency_stats(res)}
+               "subtrees_shared": srv.shared() - sh, **latency_stats(res)}
         rows.append(row)
         emit(row)
         for frac in fractions:
             rate = frac * cap
             reqs = requests(rate, seed)
+            sh = srv.shared()
             t = time.perf_counter()
             res = srv.run(reqs, realtime=True)
             wall = time.perf_counter() - t
             row = {"mode": "poisson", "load": frac, "rate_jobs_per_s": rate, "jobs": len(res), "seconds": wall,
                    "jobs_per_s": len(res) / wall, "squares_per_s": sum(r.count for r in res) / wall,
-                   "max_concurrency": max_concurrency(res), **latency_stats(res)}
+                   "max_concurrency": max_concurrency(res), "subtrees_shared": srv.shared() - sh,
+                   **latency_stats(res)}
             rows.append(row)
             emit(row)
     finally:
@@ -265,13 +272,16 @@ def main(argv=None):
     ap.add_argument("--fractions", default="0.25,0.5,0.75,0.9,1.1")
     ap.add_argument("--min-tasks", type=int, default=16384)
     ap.add_argument("--blocks-per-cu", type=int, default=2)
+    ap.add_argument("--steal-depth", type=int, default=0,
+                    help="handing of subtrees between waves: 0 = library default, < 0 = off")
     ap.add_argument("--solo", action="store_true",
                     help="instead of the sweep: each request counted alone by the batch path")
     args = ap.parse_args(argv)
     if args.solo:
         print(json.dumps(solo_times(args.jobs, args.min_tasks)), flush=True)
         return
-    with Server(min_tasks=args.min_tasks, launch={"blocks_per_cu": args.blocks_per_cu}) as srv:
+    with Server(min_tasks=args.min_tasks,
+                launch={"blocks_per_cu": args.blocks_per_cu, "steal_depth": args.steal_depth}) as srv:
         sweep(args.jobs, [float(x) for x in args.fractions.split(",")], server=srv,
               emit=lambda row: print(json.dumps(row), flush=True))
 

@@ -194,7 +194,8 @@ def _wait(h, ticket, limit_s):
 
 
 def test_grid_stays_whole_while_a_long_job_runs():
-    # A long request split into few workunits keeps a few waves busy; the
+    # A long request in one workunit keeps one wave busy (with the handing
+    # of subtrees between waves off); the
     # rest of the grid has nothing to take for longer than the idle limit
     # (50 ms) but stays, so requests submitted meanwhile are served by the
     # whole grid and finish long before the long one.  Once nothing runs,
@@ -202,17 +203,19 @@ def test_grid_stays_whole_while_a_long_job_runs():
     n = 8
     units = dls.dls_split_target(n, 0, oracle.identity_prefix(n), 400, 24)
     counts = dls.dls_count(n, 0, units)
-    pick = int(np.argmin(np.abs(np.log(np.maximum(counts, 1).astype(np.float64)) - np.log(5e6))))
+    pick = int(np.argmin(np.abs(np.log(np.maximum(counts, 1).astype(np.float64)) - np.log(2e7))))
     long_prefix, long_count = units[pick], int(counts[pick])
-    assert 1e6 <= long_count <= 5e7, long_count
+    assert 5e6 <= long_count <= 5e7, long_count
     # orders 7 and 8: their oracle counts take well under a second
     from paper_1709_02599_amd.serve import Request
     small = [Request(j.jid, j.n, j.vs, j.prefix, 0.0)
              for j in dls_workloads.job_stream(16, 1000.0, seed=13, orders=(7, 8), k_range=(14, 20))]
     want = _oracle(small)
-    h = dls.dls_server_create(max_jobs=64, pool_bytes=16 << 20)
+    # one workunit and no handing of subtrees between waves: the long job
+    # keeps the one wave that took it
+    h = dls.dls_server_create(max_jobs=64, pool_bytes=16 << 20, launch={"steal_depth": -1})
     try:
-        t_long = dls.dls_server_submit(h, n, 0, long_prefix, 64)
+        t_long = dls.dls_server_submit(h, n, 0, long_prefix, 1)
         t0 = time.time()
         time.sleep(0.2)
         live, grid = dls.dls_server_waves(h)
@@ -237,3 +240,74 @@ def test_grid_stays_whole_while_a_long_job_runs():
         assert dls.dls_server_waves(h)[0] == 0
     finally:
         dls.dls_server_destroy(h)
+
+
+def _serve_one(n, flags, prefix, min_tasks, launch=None):
+    """(count, device seconds, subtrees handed between waves) of one request
+    served alone by a fresh server."""
+    h = dls.dls_server_create(max_jobs=4, pool_bytes=4 << 20, launch=launch)
+    try:
+        t = dls.dls_server_submit(h, n, flags, prefix, min_tasks)
+        c, ticks = _wait(h, t, 120)
+        return c, (ticks[1] - ticks[0]) * 1e-8, dls.dls_server_shared(h)
+    finally:
+        dls.dls_server_destroy(h)
+
+
+def _order8_unit(lo, hi):
+    """A workunit of the order-8 first-row split whose count (batch path)
+    lies in [lo, hi], and that count."""
+    units = dls.dls_split_target(8, 0, oracle.identity_prefix(8), 400, 24)
+    counts = dls.dls_count(8, 0, units)
+    target = np.sqrt(lo * hi)
+    k = int(np.argmin(np.abs(np.log(np.maximum(counts, 1).astype(np.float64)) - np.log(target))))
+    assert lo <= counts[k] <= hi, int(counts[k])
+    return units[k], int(counts[k])
+
+
+def test_one_request_is_shared_across_waves():
+    # a request of one workunit with handing between waves on (steal_depth
+    # 8): its wave's lanes share it, and waves without work take subtrees
+    # those lanes hand on through the job's donation queue.  The count
+    # equals the oracle's (exact), and subtrees were handed on.
+    base = oracle.identity_prefix(8)
+    units = dls.dls_split_target(8, 0, base, 400, 24)
+    deeper = dls.dls_split_target(8, 0, units[0], 64, 24)
+    counts = dls.dls_count(8, 0, deeper)
+    k = int(np.argmin(np.abs(np.log(np.maximum(counts, 1).astype(np.float64)) - np.log(1.5e5))))
+    prefix = deeper[k]
+    want = oracle.count(8, prefix)
+    assert 2e4 <= want <= 1e6, want
+    c, secs, shared = _serve_one(8, 0, prefix, 1, launch={"steal_depth": 8})
+    print(f"count {c}, {secs * 1e3:.2f} ms on the device, {shared} subtrees handed between waves", flush=True)
+    assert c == want
+    assert shared > 0
+
+
+@pytest.mark.parametrize("steal", [0, -1, 2, 16])
+def test_sharing_across_waves_default_off_and_shallow(steal):
+    # the same heavy request in one workunit with the default (no handing
+    # between waves), handing off, from all but the last two levels (many
+    # small subtrees: the job's ring of 2048 records is reused many times
+    # over) and from 16 levels up: the count is unchanged
+    prefix, count = _order8_unit(1e6, 3e7)
+    c, secs, shared = _serve_one(8, 0, prefix, 1, launch={"steal_depth": steal} if steal else None)
+    print(f"steal_depth {steal}: count {c}, {secs * 1e3:.2f} ms, {shared} subtrees handed on", flush=True)
+    assert c == count
+    if steal <= 0:
+        assert shared == 0
+    else:
+        assert shared > 0
+
+
+def test_workunits_spread_over_the_grid():
+    # a request of 64 workunits: a wave takes one at a time (the job's
+    # workunits over twice the grid's waves, at least one), so 64 waves
+    # share the work and the request finishes well before the same request
+    # in one workunit does (one wave); both counts are exact
+    prefix, count = _order8_unit(1e6, 3e7)
+    c64, t64, _ = _serve_one(8, 0, prefix, 64)
+    c1, t1, _ = _serve_one(8, 0, prefix, 1)
+    print(f"count {count}: 64 workunits {t64 * 1e3:.2f} ms, one workunit {t1 * 1e3:.2f} ms", flush=True)
+    assert c64 == c1 == count
+    assert t64 < 0.5 * t1
