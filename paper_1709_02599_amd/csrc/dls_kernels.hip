@@ -1981,12 +1981,17 @@ __global__ void __launch_bounds__(256) valu_probe(int iters, uint32_t *sink) {
 //
 // LDS per wave: its descriptor table, the first level's 4-byte descriptor and
 // pattern of the job (for building records), its lanes' stacks (one row of
-// 64 slots per level) and a 64-record mailbox for sharing subtrees.
+// 64 slots per level), a 32-record mailbox for sharing subtrees (a pass
+// shares at most 32: donors are busy lanes, takers idle ones) and, for
+// order 9 without vertical symmetry, its lanes' line masks (the LDS-mask
+// layout: one 4-byte word per line and lane, lines 256 bytes apart).
 constexpr uint32_t kSvTable = 16u * 65u;  // >= 16 B x (64 + 1) (even N <= 8), 8 B x (81 + 1) (N = 9)
 constexpr uint32_t kSvInfo = 64u;         // patbits[8], first descriptor, levels
 constexpr uint32_t kSvStacks = 82u * 128u;  // (81 + 1) rows x 64 lanes x 2 bytes
-constexpr uint32_t kSvMbox = 64u * 48u;     // 64 records of order 9
-constexpr uint32_t kSvWave = kSvTable + kSvInfo + kSvStacks + kSvMbox;
+constexpr uint32_t kSvMbox = 32u * 48u;     // 32 records of order 9
+constexpr uint32_t kSvLine = 64u * 4u;      // bytes between two lines' mask words
+constexpr uint32_t kSvMasks = 9u * kSvLine; // 9 packed lines (order 9)
+constexpr uint32_t kSvWave = kSvTable + kSvInfo + kSvStacks + kSvMbox + kSvMasks;
 constexpr int kSvBlock = 256;
 constexpr uint32_t kSvPoll = 4;   // passes between a full wave's looks at the donation queue
 constexpr int kSvShareMin = 8;    // idle lanes that start sharing inside a wave
@@ -2014,12 +2019,18 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     using DT = VLaneDesc<N, VS>;
     using R = Rec<N, VS>;
     using G = Geo<N, VS>;
-    constexpr uint32_t DB = DT::DB;
+    // order 9 (plain; with vertical symmetry every order-9 count is 0 and is
+    // answered on the host) keeps its line masks in LDS, as the batch path
+    // does from order 9 on; smaller orders keep them in VGPRs
+    constexpr bool LM = N >= 9 && !VS;
+    using LaneT = typename std::conditional<LM, LdsLane<N, VS>, VLane<N, VS>>::type;
+    static_assert(!LM || LdsLane<N, VS>::LINES * kSvLine <= kSvMasks, "line masks");
+    constexpr uint32_t DB = LM ? LdsLane<N, VS>::DB : DT::DB;
     constexpr int NN = N * N;
     constexpr int PS = (NN + 15) & ~15;  // pre_stride(N)
     static_assert(DB * (uint32_t)(NN + 1) <= kSvTable, "descriptor table");
     static_assert((uint32_t)(NN + 1) * 64u * sizeof(S) <= kSvStacks, "stacks");
-    static_assert(64u * sizeof(R) <= kSvMbox, "mailbox");
+    static_assert(32u * sizeof(R) <= kSvMbox, "mailbox");
     static_assert(sizeof(R) <= (size_t)kServeItemBytes, "donation record");
     const uint64_t below = (1ull << lane) - 1ull;
     const JobDesc *jd = &a.jobs[slot];
@@ -2053,7 +2064,14 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     for (int k = lane; k < nlev; k += 64) {
         const uint32_t d = hload32(&jd->plan.desc[k]);
         const uint32_t keep = (N <= 8 && k != nlev - 1) ? G::ALL : 0u;
-        if constexpr (DT::DW) {
+        if constexpr (LM) {
+            // row and column word offsets of the level's cell, then its diagonals
+            const uint32_t i = ((d >> 6) & 3u) * G::LPW + (d & 63u) / N;
+            const uint32_t j = ((d >> 14) & 3u) * G::LPW + ((d >> 8) & 63u) / N;
+            const uint32_t roff = i * kSvLine, coff = (LdsLane<N, VS>::PACK ? j : N + j) * kSvLine;
+            reinterpret_cast<uint2 *>(wsm)[k] =
+                make_uint2(roff | (coff << 16), (d_md(d) & G::ALL) | ((d_ad(d) & G::ALL) << 16));
+        } else if constexpr (DT::DW) {
             const uint32_t z = (d >> 16) & 1u ? 0u : ((d >> 17) & 1u ? 8u : kDwNone);
             reinterpret_cast<uint4 *>(wsm)[k] = make_uint4(d & 63u, (d >> 8) & 63u, z, 0u);
         } else {
@@ -2095,16 +2113,22 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     for (int k = 0; k < 8; ++k) patbits[k] = info[k];
     const uint32_t desc0 = info[8];
 
-    VLane<N, VS> L;
+    LaneT L;
+    if constexpr (LM) {
+        L.md = L.ad2 = 0u;
+        L.mbase = dbase + kSvTable + kSvInfo + kSvStacks + kSvMbox + (uint32_t)lane * 4u;
+        L.cur = lds_ld2(dbase);
+    } else {
 #pragma unroll
-    for (int k = 0; k < G::WR; ++k) L.R[k] = 0;
+        for (int k = 0; k < G::WR; ++k) L.R[k] = 0;
 #pragma unroll
-    for (int k = 0; k < G::WC; ++k) L.C[k] = 0;
-    L.mdh = L.adh = 0u;
+        for (int k = 0; k < G::WC; ++k) L.C[k] = 0;
+        L.mdh = L.adh = 0u;
+        L.cur = DT::load(dbase);
+    }
     L.cand = 0u;
     L.da = L.da0 = dbase;
     L.sa = lane_off;
-    L.cur = DT::load(dbase);
     L.cnt = 0;
     L.c32 = 0u;
     bool has = false;
@@ -2121,8 +2145,13 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
     share = share < chunk ? share : chunk;
     share = share > 1u ? share : 1u;
     auto start = [&](const R &r) {
-        L.from_rec(r, dbase, last, lane_off, stride);
+        if constexpr (LM) L.from_rec(r, dbase, last, lane_off, stride, kSvLine);
+        else L.from_rec(r, dbase, last, lane_off, stride);
         lds_st<S>(L.sa, (S)0);
+    };
+    auto give = [&](int lvl) -> R {
+        if constexpr (LM) return L.donate(lvl, dbase, slot_of, 0u, kSvLine);
+        else return L.donate(lvl, dbase, slot_of, 0u);
     };
 
     for (;;) {
@@ -2238,7 +2267,7 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
                         // a record never published stays outstanding: the job is then never reported done
                         if (free) {
                             __hip_atomic_fetch_add(&js->remaining, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            items[e] = L.donate(lvl, dbase, slot_of, 0u);
+                            items[e] = give(lvl);
                             __hip_atomic_store(&ready[e], tag | (2ull * lap + 1ull), __ATOMIC_RELEASE,
                                                __HIP_MEMORY_SCOPE_AGENT);
                         }
@@ -2323,7 +2352,7 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
                 const uint64_t drank = (uint64_t)__popcll(donors & below);
                 const uint64_t rrank = (uint64_t)__popcll(want & below);
                 const bool take = !has && rrank < m;
-                if (lvl >= 0 && drank < m) mbox[drank] = L.donate(lvl, dbase, slot_of, 0u);
+                if (lvl >= 0 && drank < m) mbox[drank] = give(lvl);
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 R got{};
