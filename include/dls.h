@@ -401,7 +401,7 @@ int dls_valu_probe(int blocks, int iters, uint32_t *d_sink, void *stream);
 typedef struct dls_server dls_server;
 
 /* launch (may be NULL): blocks_per_cu (1 or 2 workgroups of 256 per CU;
- * default 2), refill_every (default 64), chunk_min = most workunits a wave
+ * default 1: the request mix ran twice as fast as with 2), refill_every (default 64), chunk_min = most workunits a wave
  * takes from a job at once (default 64; a wave takes about the job's
  * workunits over twice the grid's waves, at least one), order_variant (fill
  * order), steal_depth

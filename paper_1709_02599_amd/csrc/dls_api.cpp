@@ -1147,7 +1147,7 @@ int dls_server_create(int max_jobs, int64_t pool_bytes, const dls_launch *launch
     if (max_jobs < 1 || max_jobs > dlsk::kServeMaxJobs || pool_bytes < 16 || pool_bytes > (int64_t(1) << 36))
         return DLS_EINVAL;
     const int variant = launch ? launch->order_variant : 0;
-    const int bpc = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 2;
+    const int bpc = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 1;
     const int refill = (launch && launch->refill_every) ? launch->refill_every : 64;
     const int chunk = (launch && launch->chunk_min) ? launch->chunk_min : 64;
     const int steal = launch ? launch->steal_depth : 0;

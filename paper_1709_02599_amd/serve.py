@@ -271,7 +271,7 @@ def main(argv=None):
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--fractions", default="0.25,0.5,0.75,0.9,1.1")
     ap.add_argument("--min-tasks", type=int, default=16384)
-    ap.add_argument("--blocks-per-cu", type=int, default=2)
+    ap.add_argument("--blocks-per-cu", type=int, default=1)
     ap.add_argument("--steal-depth", type=int, default=0,
                     help="handing of subtrees between waves: 0 = library default, < 0 = off")
     ap.add_argument("--solo", action="store_true",
