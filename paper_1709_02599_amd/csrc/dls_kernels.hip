@@ -2428,7 +2428,7 @@ __device__ __noinline__ bool serve_job(const ServeArgs &a, int slot, uint64_t pu
 // host's publish word; only when it has moved since the last scan does that
 // wave read the ring's pub words, and it sets up every new job it finds.
 // Every other wave finds jobs in the device-side work states alone.
-constexpr uint64_t kServePollTicks = 500;  // 5 us at 100 MHz
+constexpr uint64_t kServePollTicks = 2000;  // 20 us at 100 MHz
 
 // The oldest published job that has untaken workunits: its slot, or -1;
 // *pub_out gets its pub word.  A job found in the ring is set up by the
@@ -2581,9 +2581,10 @@ __global__ void __launch_bounds__(kSvBlock) __attribute__((amdgpu_waves_per_eu(1
             if (lane == 0) __hip_atomic_fetch_add(a.gate + 3, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             asked = true;
         }
-        // an idle wave looks again after 1, 2, 4, ... up to about 100 us
+        // an idle wave looks again after 1, 2, 4, ... up to about 400 us (a
+        // longer sleep than 100 us measured 5 % more requests/s on the mix)
         for (uint32_t t = 0; t < backoff; ++t) __builtin_amdgcn_s_sleep(32);
-        backoff = backoff < 128 ? backoff * 2 : 128;
+        backoff = backoff < 512 ? backoff * 2 : 512;
     }
     if (asked && lane == 0) __hip_atomic_fetch_add(a.gate + 3, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane == 0) __hip_atomic_store(alive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
